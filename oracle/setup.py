@@ -1,0 +1,44 @@
+"""Mesh / physics description used by every oracle routine (test infrastructure)."""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+PERIODIC, OUTFLOW = 0, 1
+IDEAL, TM = 0, 1
+NEWTON, QUARTIC, CUBIC, BRENT = 0, 1, 2, 3
+
+
+@dataclass
+class Setup:
+    dim: int
+    p: int
+    n_elem: tuple = (1, 1, 1)
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    eos: int = IDEAL
+    gamma_ad: float = 4.0 / 3.0
+    c: float = 1.0
+    c2p: int = -1            # -1: the paper's default solver for the EOS (Newton / cubic)
+    phys_eps: float = 1e-12
+    extra: dict = field(default_factory=dict)
+
+    @staticmethod
+    def from_config(cfg: dict) -> "Setup":
+        return Setup(dim=cfg["dim"], p=cfg["p"], n_elem=tuple(cfg["n_elem"]), lo=tuple(cfg["lo"]),
+                     hi=tuple(cfg["hi"]), bc=tuple(cfg["bc"]), eos=cfg["eos"],
+                     gamma_ad=cfg["gamma_ad"], c=cfg["c"], c2p=cfg["c2p"])
+
+    @property
+    def nvar(self) -> int:
+        return 2 + self.dim
+
+    def dx(self, d: int) -> float:
+        return (self.hi[d] - self.lo[d]) / self.n_elem[d]
+
+    def shape(self) -> tuple:
+        """[nez, ney, nex, nk, nj, ni] of one nodal component."""
+        q = self.p + 1
+        nx, ny, nz = self.n_elem
+        return (nz if self.dim > 2 else 1, ny if self.dim > 1 else 1, nx,
+                q if self.dim > 2 else 1, q if self.dim > 1 else 1, q)

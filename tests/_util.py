@@ -1,0 +1,24 @@
+"""Small helpers shared by the tests (no method arithmetic)."""
+import numpy as np
+import torch
+
+from oracle.setup import Setup
+from oracle import srhd
+from paper_2205_00095_amd import workloads as wl
+
+
+def oracle_state(cfg, seed=None):
+    """(Setup, U) for a workload: the oracle's own prim->cons of the seeded primitives."""
+    st = Setup.from_config(cfg)
+    rho, v, P = wl.initial_primitives(cfg, seed)
+    U = srhd.prim3_to_cons(torch.from_numpy(rho), torch.from_numpy(v), torch.from_numpy(P), st)
+    return st, U.reshape((st.nvar,) + wl.field_shape(cfg))
+
+
+def rel_err_per_var(a, b):
+    """max_k ||a_k - b_k||_inf / ||b_k||_inf over conserved components k."""
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    num = (a - b).abs().max(1).values
+    den = b.abs().max(1).values.clamp(min=1e-300)
+    return (num / den)

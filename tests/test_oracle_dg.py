@@ -1,0 +1,141 @@
+"""Pins of the oracle's DG right-hand side (Sec. 2.3, 2.4) against invariants and reductions."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import con2prim as cp
+from oracle import dg, srhd
+from oracle.setup import IDEAL, OUTFLOW, PERIODIC, TM, Setup
+
+
+def _random_state(st, rng, gmax=3.0, smooth=False):
+    shape = st.shape()
+    if smooth:
+        # smooth periodic field over the mesh (sin of node coordinates)
+        q = st.p + 1
+        xi, _ = np.polynomial.legendre.leggauss(q)
+        coords = []
+        for d in range(3):
+            n = st.n_elem[d] if d < st.dim else 1
+            if d < st.dim:
+                pos = (np.arange(n)[:, None] + 0.5 * (xi[None] + 1)) / n
+            else:
+                pos = np.zeros((1, 1))
+            b = [1] * 6
+            b[2 - d], b[5 - d] = pos.shape
+            coords.append(np.broadcast_to(pos.reshape(b), shape))
+        ph = sum(2 * np.pi * coords[d] * (d + 1) for d in range(st.dim))
+        rho = 1.0 + 0.3 * np.sin(ph)
+        P = 1.0 + 0.2 * np.cos(ph)
+        v = np.stack([0.3 * np.cos(ph + d) for d in range(st.dim)])
+    else:
+        rho = 10 ** rng.uniform(-0.5, 0.5, shape)
+        P = 10 ** rng.uniform(-0.5, 0.5, shape)
+        g = rng.uniform(1.0, gmax, shape)
+        nv = rng.standard_normal((st.dim,) + shape)
+        nv /= np.sqrt((nv ** 2).sum(0))
+        v = nv * np.sqrt(1 - 1 / g ** 2)
+    return srhd.prim3_to_cons(torch.tensor(rho), torch.tensor(v), torch.tensor(P), st)
+
+
+CASES = [(1, 2, IDEAL), (1, 0, TM), (2, 1, TM), (2, 3, IDEAL), (2, 2, TM), (3, 2, IDEAL), (3, 1, TM)]
+
+
+@pytest.mark.parametrize("dim,p,eos", CASES)
+def test_uniform_state_gives_zero(dim, p, eos):
+    st = Setup(dim=dim, p=p, n_elem=(4, 3, 2)[:dim] + (1,) * (3 - dim), eos=eos,
+               bc=(PERIODIC, OUTFLOW, PERIODIC))
+    rng = np.random.default_rng(dim * 10 + p)
+    U0 = _random_state(Setup(dim=dim, p=0, eos=eos), rng)  # one random state
+    U = U0.reshape(st.nvar, *([1] * 6)).expand((st.nvar,) + st.shape()).clone()
+    R = dg.rhs(U, st)
+    W, _ = cp.con2prim(U, st)
+    fmax = max(float(srhd.flux(W, d, st).abs().max()) * 2 / st.dx(d) for d in range(dim))
+    assert float(R.abs().max()) <= 1e-13 * fmax * (p + 1) ** 2
+
+
+@pytest.mark.parametrize("dim,p,eos", CASES)
+def test_discrete_conservation_periodic(dim, p, eos):
+    st = Setup(dim=dim, p=p, n_elem=(5, 4, 3)[:dim] + (1,) * (3 - dim), eos=eos)
+    U = _random_state(st, np.random.default_rng(7))
+    R = dg.rhs(U, st)
+    wR = R * dg.elem_weights(st)
+    tot = wR.sum((1, 2, 3, 4, 5, 6))
+    scale = wR.abs().sum((1, 2, 3, 4, 5, 6))
+    assert float((tot.abs() / scale).max()) < 1e-13
+
+
+def test_mirror_symmetry_x():
+    st = Setup(dim=2, p=2, n_elem=(6, 5, 1), eos=TM, bc=(PERIODIC, OUTFLOW, PERIODIC))
+    U = _random_state(st, np.random.default_rng(8))
+
+    def mirror(A):
+        B = A.flip(3).flip(6).clone()
+        B[1] = -B[1]
+        return B
+
+    R = dg.rhs(U, st)
+    Rm = dg.rhs(mirror(U), st)
+    assert torch.allclose(Rm, mirror(R), rtol=1e-12, atol=1e-12 * float(R.abs().max()))
+
+
+def test_axis_swap_symmetry_2d():
+    st = Setup(dim=2, p=3, n_elem=(4, 4, 1), eos=IDEAL)
+    U = _random_state(st, np.random.default_rng(9))
+
+    def swap(A):
+        B = A.transpose(2, 3).transpose(5, 6).clone()
+        B[[1, 2]] = B[[2, 1]]
+        return B
+
+    R = dg.rhs(U, st)
+    Rs = dg.rhs(swap(U), st)
+    assert torch.allclose(Rs, swap(R), rtol=1e-12, atol=1e-12 * float(R.abs().max()))
+
+
+@pytest.mark.parametrize("eos", [IDEAL, TM])
+def test_2d_constant_in_y_equals_1d(eos):
+    p = 2
+    st1 = Setup(dim=1, p=p, n_elem=(7, 1, 1), eos=eos)
+    st2 = Setup(dim=2, p=p, n_elem=(7, 3, 1), eos=eos, hi=(1.0, 0.4, 1.0),
+                bc=(PERIODIC, OUTFLOW, PERIODIC))
+    U1 = _random_state(st1, np.random.default_rng(10))
+    # embed: (D, Sx, tau) -> (D, Sx, 0, tau), constant along y
+    U2 = torch.zeros((4,) + st2.shape())
+    for k2, k1 in ((0, 0), (1, 1), (3, 2)):
+        U2[k2] = U1[k1].expand(1, 3, 7, 1, p + 1, p + 1)
+    R1 = dg.rhs(U1, st1)
+    R2 = dg.rhs(U2, st2)
+    scale = float(R1.abs().max())
+    for k2, k1 in ((0, 0), (1, 1), (3, 2)):
+        assert torch.allclose(R2[k2], R1[k1].expand_as(R2[k2]), atol=1e-13 * scale)
+    assert float(R2[2].abs().max()) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("eos", [IDEAL, TM])
+def test_p0_is_first_order_hll_finite_volume(eos):
+    """p = 0 removes the volume term: R_e = -(F(U_e, U_e+1) - F(U_e-1, U_e))/dx (Sec. 2.3)."""
+    n = 9
+    st = Setup(dim=1, p=0, n_elem=(n, 1, 1), eos=eos, hi=(2.0, 1.0, 1.0))
+    U = _random_state(st, np.random.default_rng(12), gmax=5.0)
+    R = dg.rhs(U, st)
+    W, _ = cp.con2prim(U, st)
+    Wc = W.reshape(3, n)
+    ref = torch.zeros(3, n)
+    for e in range(n):
+        left = srhd.hll(Wc[:, (e - 1) % n, None], Wc[:, e, None], 0, st)[:, 0]
+        right = srhd.hll(Wc[:, e, None], Wc[:, (e + 1) % n, None], 0, st)[:, 0]
+        ref[:, e] = -(right - left) / st.dx(0)
+    assert torch.allclose(R.reshape(3, n), ref, rtol=1e-13, atol=1e-13)
+
+
+def test_outflow_boundary_face_uses_interior_flux():
+    """Outflow: the boundary face flux is the physical flux of the interior trace."""
+    st = Setup(dim=1, p=0, n_elem=(3, 1, 1), eos=IDEAL, bc=(OUTFLOW, PERIODIC, PERIODIC))
+    U = _random_state(st, np.random.default_rng(13))
+    W, _ = cp.con2prim(U, st)
+    Wc = W.reshape(3, 3)
+    R = dg.rhs(U, st).reshape(3, 3)
+    f0 = srhd.flux(Wc[:, :1], 0, st)[:, 0]
+    f01 = srhd.hll(Wc[:, 0, None], Wc[:, 1, None], 0, st)[:, 0]
+    assert torch.allclose(R[:, 0], -(f01 - f0) / st.dx(0), rtol=1e-13, atol=1e-13)
