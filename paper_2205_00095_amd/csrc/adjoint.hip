@@ -1,0 +1,221 @@
+// Host side of the adjoint entry points: dg_rhs_vjp, the taped SSP-RK3 step and
+// its vector-Jacobian product, the v_y^2 objective and the initial-data adjoint.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "ctx.hpp"
+#include "launch_adj.hpp"
+
+using namespace dgsrhd;
+
+namespace {
+
+size_t state_doubles(const dg_ctx* c) { return (size_t)c->nv * (size_t)c->ntot; }
+int obj_blocks(const dg_ctx* c) { return (int)((c->ntot + 255) / 256); }
+
+// Adjoint scratch: Utmp, a 6-state tape, mu_a, mu_b, lamn, then objective partials.
+enum { A_UTMP = 0, A_TAPE = 1, A_MUA = 7, A_MUB = 8, A_LAMN = 9, A_NSTATES = 10 };
+
+int ensure_adj(dg_ctx* c) {
+  const size_t need = A_NSTATES * state_doubles(c) + (size_t)obj_blocks(c) + 8;
+  if (c->adj && c->adj_doubles >= need) return DG_OK;
+  if (c->adj) {
+    int r = hipcheck(c, hipStreamSynchronize(c->stream), "adjoint scratch");
+    if (r) return r;
+    (void)hipFree(c->adj);
+    c->adj = nullptr;
+  }
+  if (hipMalloc((void**)&c->adj, need * sizeof(double)) != hipSuccess) {
+    c->adj = nullptr;
+    return fail(c, DG_ENOMEM, "adjoint scratch allocation (%zu doubles) failed", need);
+  }
+  c->adj_doubles = need;
+  return DG_OK;
+}
+
+double* adj_state(dg_ctx* c, int k) { return c->adj + (size_t)k * state_doubles(c); }
+
+hipError_t L_vjp(dg_ctx* c, int mode, const VjpArgs& a) {
+  const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos;
+  if (dim == 1) return launch_vjp_dim1(p, eos, mode, a, c->stream);
+  if (dim == 2) return launch_vjp_dim2(p, eos, mode, a, c->stream);
+  return launch_vjp_dim3(p, eos, mode, a, c->stream);
+}
+
+hipError_t L_enforce_vjp(dg_ctx* c, const double* Pst, const double* lin, double* lout) {
+  const int dim = c->desc.dim, p = c->desc.p;
+  if (dim == 1) return launch_enforce_vjp_dim1(p, Pst, lin, lout, c->m, c->t, c->q, c->stream);
+  if (dim == 2) return launch_enforce_vjp_dim2(p, Pst, lin, lout, c->m, c->t, c->q, c->stream);
+  return launch_enforce_vjp_dim3(p, Pst, lin, lout, c->m, c->t, c->q, c->stream);
+}
+
+VjpArgs vjp_args(dg_ctx* c) {
+  VjpArgs a{};
+  a.m = c->m;
+  a.t = c->t;
+  a.q = c->q;
+  return a;
+}
+
+__global__ void k_sum_partials(const double* partial, int n, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// One forward step in place, recording (W(U^n), W(U1), W(U2), P1, P2, P3).
+int step_tape(dg_ctx* c, double* U, double dt, double* tape, const char* what) {
+  const size_t S = state_doubles(c);
+  double* W0 = tape;
+  double* W1 = tape + S;
+  double* W2 = tape + 2 * S;
+  double* P1 = tape + 3 * S;
+  double* P2 = tape + 4 * S;
+  double* P3 = tape + 5 * S;
+  int r = hipcheck(c, L_con2prim(c, U, W0), what);
+  if (r) return r;
+  ElemArgs a = base_args(c);
+  a.dt = dt;
+  a.W = W0; a.Uk = U; a.Un = U; a.ca = 0.0; a.cb = 1.0; a.out = c->U1; a.Wout = W1; a.Pout = P1;
+  if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+  a.W = W1; a.Uk = c->U1; a.ca = 0.75; a.cb = 0.25; a.out = c->U2; a.Wout = W2; a.Pout = P2;
+  if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+  a.W = W2; a.Uk = c->U2; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.out = U; a.Wout = nullptr; a.Pout = P3;
+  return hipcheck(c, L_element(c, MODE_STAGE, a), what);
+}
+
+// Reverse of one taped step: lam_n = (dU^{n+1}/dU^n)^T lam_next.
+int step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_next, double* lam_n,
+                  const char* what) {
+  const size_t S = state_doubles(c);
+  const double* W0 = tape;
+  const double* W1 = tape + S;
+  const double* W2 = tape + 2 * S;
+  const double* P1 = tape + 3 * S;
+  const double* P2 = tape + 4 * S;
+  const double* P3 = tape + 5 * S;
+  double* mua = adj_state(c, A_MUA);
+  double* mub = adj_state(c, A_MUB);
+  double* lamn = adj_state(c, A_LAMN);
+  const bool phys = c->desc.phys != 0;
+  int r;
+  const double* mu3 = lam_next;
+  if (phys) {
+    if ((r = hipcheck(c, L_enforce_vjp(c, P3, lam_next, mua), what))) return r;
+    mu3 = mua;
+  }
+  VjpArgs a = vjp_args(c);
+  a.dt = dt;
+  // stage 3: U^{n+1} = Pi(1/3 U^n + 2/3 (U2 + dt R(U2)))
+  a.W = W2; a.lam = mu3; a.out = mub; a.lamn = lamn; a.lamn_init = 1;
+  a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.Pprev = phys ? P2 : nullptr;
+  if ((r = hipcheck(c, L_vjp(c, VJP_STAGE, a), what))) return r;
+  // stage 2: U2 = Pi(3/4 U^n + 1/4 (U1 + dt R(U1)))
+  double* mu1 = mua;  // mu3 (mua or lam_next) is no longer read
+  a.W = W1; a.lam = mub; a.out = mu1; a.lamn_init = 0; a.ca = 0.75; a.cb = 0.25; a.Pprev = phys ? P1 : nullptr;
+  if ((r = hipcheck(c, L_vjp(c, VJP_STAGE, a), what))) return r;
+  // stage 1: U1 = Pi(U^n + dt R(U^n))
+  a.W = W0; a.lam = mu1; a.out = lam_n; a.ca = 0.0; a.cb = 1.0; a.Pprev = nullptr;
+  return hipcheck(c, L_vjp(c, VJP_STAGE, a), what);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_rhs_vjp(dg_ctx* c, const double* U, const double* lamR, double* lamU) {
+  if (!c) return DG_EINVAL;
+  if (!U || !lamR || !lamU) return fail(c, DG_EINVAL, "dg_rhs_vjp: null pointer");
+  if (lamU == lamR || lamU == U) return fail(c, DG_EINVAL, "dg_rhs_vjp: output aliases an input");
+  int r = hipcheck(c, L_con2prim(c, U, c->Wa), "dg_rhs_vjp/con2prim");
+  if (r) return r;
+  VjpArgs a = vjp_args(c);
+  a.W = c->Wa;
+  a.lam = lamR;
+  a.out = lamU;
+  if ((r = hipcheck(c, L_vjp(c, VJP_PLAIN, a), "dg_rhs_vjp"))) return r;
+  return finish(c, "dg_rhs_vjp");
+}
+
+size_t dg_tape_size(const dg_ctx* c) { return c ? 6 * state_doubles(c) : 0; }
+
+int dg_ssprk3_step_tape(dg_ctx* c, double* U, double dt, double* tape) {
+  if (!c) return DG_EINVAL;
+  if (!U || !tape) return fail(c, DG_EINVAL, "dg_ssprk3_step_tape: null pointer");
+  int r = step_tape(c, U, dt, tape, "dg_ssprk3_step_tape");
+  if (r) return r;
+  return finish(c, "dg_ssprk3_step_tape");
+}
+
+int dg_ssprk3_step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_next, double* lam_n) {
+  if (!c) return DG_EINVAL;
+  if (!tape || !lam_next || !lam_n) return fail(c, DG_EINVAL, "dg_ssprk3_step_vjp_tape: null pointer");
+  int r = ensure_adj(c);
+  if (r) return r;
+  if ((r = step_vjp_tape(c, tape, dt, lam_next, lam_n, "dg_ssprk3_step_vjp_tape"))) return r;
+  return finish(c, "dg_ssprk3_step_vjp_tape");
+}
+
+int dg_ssprk3_step_vjp(dg_ctx* c, const double* Un, double dt, const double* lam_next, double* lam_n) {
+  if (!c) return DG_EINVAL;
+  if (!Un || !lam_next || !lam_n) return fail(c, DG_EINVAL, "dg_ssprk3_step_vjp: null pointer");
+  int r = ensure_adj(c);
+  if (r) return r;
+  double* Ut = adj_state(c, A_UTMP);
+  double* tape = adj_state(c, A_TAPE);
+  r = hipcheck(c, hipMemcpyAsync(Ut, Un, state_doubles(c) * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+               "dg_ssprk3_step_vjp");
+  if (r) return r;
+  if ((r = step_tape(c, Ut, dt, tape, "dg_ssprk3_step_vjp"))) return r;
+  if ((r = step_vjp_tape(c, tape, dt, lam_next, lam_n, "dg_ssprk3_step_vjp"))) return r;
+  return finish(c, "dg_ssprk3_step_vjp");
+}
+
+int dg_objective_vy2(dg_ctx* c, const double* U, double* J_host, double* dJdU) {
+  if (!c) return DG_EINVAL;
+  if (!U || !J_host) return fail(c, DG_EINVAL, "dg_objective_vy2: null pointer");
+  int r = ensure_adj(c);
+  if (r) return r;
+  const int nb = obj_blocks(c);
+  double* partial = c->adj + A_NSTATES * state_doubles(c);
+  double* Jdev = partial + nb;
+  double jac = 1.0;
+  for (int d = 0; d < c->desc.dim; ++d) jac *= 1.0 / c->m.two_dx[d];  // prod dx_d / 2
+  const int dim = c->desc.dim, eos = c->desc.eos, n1 = c->desc.p + 1;
+  hipError_t e;
+  if (dim == 1) e = launch_objective_dim1(eos, U, partial, dJdU, c->ntot, c->npe, n1, c->t, jac, c->q, nb, c->stream);
+  else if (dim == 2)
+    e = launch_objective_dim2(eos, U, partial, dJdU, c->ntot, c->npe, n1, c->t, jac, c->q, nb, c->stream);
+  else e = launch_objective_dim3(eos, U, partial, dJdU, c->ntot, c->npe, n1, c->t, jac, c->q, nb, c->stream);
+  if ((r = hipcheck(c, e, "dg_objective_vy2"))) return r;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c->stream, partial, nb, Jdev);
+  if ((r = hipcheck(c, hipGetLastError(), "dg_objective_vy2"))) return r;
+  if ((r = hipcheck(c, hipMemcpyAsync(J_host, Jdev, sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                    "dg_objective_vy2")))
+    return r;
+  if ((r = hipcheck(c, hipStreamSynchronize(c->stream), "dg_objective_vy2"))) return r;
+  return finish(c, "dg_objective_vy2");
+}
+
+int dg_set_state_vjp(dg_ctx* c, const double* src, const double* lamU, double* lamS) {
+  if (!c) return DG_EINVAL;
+  if (!src || !lamU || !lamS) return fail(c, DG_EINVAL, "dg_set_state_vjp: null pointer");
+  const int dim = c->desc.dim, eos = c->desc.eos;
+  hipError_t e;
+  if (dim == 1) e = launch_prim3_vjp_dim1(eos, src, lamU, lamS, c->ntot, c->q, c->stream);
+  else if (dim == 2) e = launch_prim3_vjp_dim2(eos, src, lamU, lamS, c->ntot, c->q, c->stream);
+  else e = launch_prim3_vjp_dim3(eos, src, lamU, lamS, c->ntot, c->q, c->stream);
+  int r = hipcheck(c, e, "dg_set_state_vjp");
+  if (r) return r;
+  return finish(c, "dg_set_state_vjp");
+}
+
+}  // extern "C"

@@ -1,0 +1,491 @@
+// Adjoint (vector-Jacobian product) kernels of the DG SRHD path.
+//
+// k_rhs_vjp    element-tile kernel, one node per lane, gather form (no atomics):
+//              transposed volume contraction and nodal-flux reverse; per face point
+//              the adjoint of the face flux is assembled from the lift transposes of
+//              BOTH adjacent elements (the neighbour's lambda gathered from HBM), the
+//              HLL flux is reversed for the element's own trace, the trace
+//              interpolation is transposed in LDS, and the recovery is reversed by the
+//              implicit-function theorem (a DIM+2 linear solve per node).
+//              Stage mode also folds in the SSP-RK combine transpose and the
+//              physicality operator's active-branch adjoint of the previous stage.
+// k_enforce_vjp  the physicality operator's adjoint alone.
+// k_objective / k_sum   J = int v_y^2 with a fixed-order reduction, and dJ/dU.
+// k_prim3_vjp  adjoint of the (rho, v, P) -> U map of the initial data.
+#pragma once
+#include "kernels.hpp"
+#include "physics_rev.hpp"
+
+namespace dgsrhd {
+
+struct VjpArgs {
+  const double* W;      // primitives of the linearisation point
+  const double* lam;    // adjoint of R (plain) or of the stage's pre-operator output (stage)
+  double* out;          // lambda_U (plain); previous stage's adjoint or lambda_n (stage)
+  double* lamn;         // running adjoint of U^n (stage mode)
+  const double* Pprev;  // pre-operator state of the previous stage (stage mode), or null
+  double ca, cb, dt;
+  int lamn_init;        // 1: lamn is treated as zero on input
+  MeshArgs m;
+  Tables t;
+  PhysParams q;
+};
+
+enum { VJP_PLAIN = 0, VJP_STAGE = 1 };
+
+template <int DIM>
+__device__ __forceinline__ bool is_floor_state(const double* W, const PhysParams& q) {
+  bool f = (W[0] == kRhoFloor) && (W[DIM + 1] == kPFloor * q.c2);
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) f = f && (W[1 + j] == 0.0);
+  return f;
+}
+
+// Nodal fluxes F^d(W), d = 0..DIM-1, reversed with one state evaluation.
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void nodal_flux_rev(const double* W, const PhysParams& q, const double (*lamF)[DIM + 2],
+                                               double* lamW) {
+  constexpr int NV = DIM + 2;
+  StateEval<EOS, DIM> s;
+  eval_state<EOS, DIM>(W, q, s);
+  double lam_U[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) lam_U[k] = 0.0;
+  double lam_ig = 0.0, lam_P = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double vd = W[1 + d] * s.ig;
+    double lam_vd = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      lam_U[k] += lamF[d][k] * vd;
+      lam_vd += lamF[d][k] * s.U[k];
+    }
+    lam_P += lamF[d][1 + d] + lamF[d][NV - 1] * vd;
+    lam_vd += lamF[d][NV - 1] * s.P;
+    lamW[1 + d] += lam_vd * s.ig;
+    lam_ig += lam_vd * W[1 + d];
+  }
+  lamW[NV - 1] += lam_P;
+  eval_state_rev<EOS, DIM>(W, q, lam_U, 0.0, lam_ig, 0.0, 0.0, lamW);
+}
+
+// Adjoint of the physicality operator on the elements of one workgroup.  Pn is
+// the node's pre-operator state; lam holds the adjoint of the operator output on
+// entry and of its input on exit.  Linearised on the active branch: the
+// element's argmin node, its stage-1/stage-2 case and the average.  sbuf needs
+// (NV + 1) * NT doubles, sred NV * EPB doubles, sflag NT ints.  All threads of
+// the block must reach it.
+template <int DIM, int P>
+__device__ __forceinline__ void physicality_vjp_block(const double* Pn, double* lam, bool act, int tid, int el,
+                                                      int node, const Tables& t, const PhysParams& q, double* sbuf,
+                                                      double* sred, int* sflag) {
+  using G = Geo<DIM, P>;
+  constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, N1 = G::N1;
+  const bool bad = act && !admissible<DIM>(Pn, q);
+  if (!__syncthreads_or(bad)) return;
+  double wn = t.w[node_coord<N1>(node, 0)];
+  if (DIM > 1) wn *= t.w[node_coord<N1>(node, 1)];
+  if (DIM > 2) wn *= t.w[node_coord<N1>(node, 2)];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sbuf[v * NT + tid] = wn * Pn[v];
+  sflag[tid] = bad ? 1 : 0;
+  __syncthreads();
+  bool eflag = false;
+  for (int n = 0; n < NPE; ++n) eflag |= (sflag[el * NPE + n] != 0);
+  double Ub[NV];
+  bool avg_ok = false;
+  double si = 1.0;
+  if (act && eflag) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+      for (int n = 0; n < NPE; ++n) acc += sbuf[v * NT + el * NPE + n];
+      Ub[v] = acc * t.inv_wsum;
+    }
+    avg_ok = admissible<DIM>(Ub, q);
+    if (avg_ok) si = node_factor<DIM>(Pn, Ub, q);
+  }
+  __syncthreads();
+  sbuf[tid] = si;
+  __syncthreads();
+  double smin = 1.0;
+  int istar = 0;
+  if (act && eflag && avg_ok) {
+    for (int n = 0; n < NPE; ++n) {
+      const double sv = sbuf[el * NPE + n];
+      if (sv < smin) { smin = sv; istar = n; }
+    }
+  }
+  __syncthreads();
+  double ls = 0.0;
+  if (act && eflag && avg_ok) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ls += lam[v] * (Pn[v] - Ub[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sbuf[v * NT + tid] = lam[v];
+  sbuf[NV * NT + tid] = ls;
+  __syncthreads();
+  double sumlam[NV], gP[NV];
+  double lam_s = 0.0;
+  const bool active = act && eflag && avg_ok && smin < 1.0;
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+      for (int n = 0; n < NPE; ++n) acc += sbuf[v * NT + el * NPE + n];
+      sumlam[v] = acc;
+    }
+    for (int n = 0; n < NPE; ++n) lam_s += sbuf[NV * NT + el * NPE + n];
+    if (node == istar) {
+      constexpr int ND = 2 * NV;
+      Dual<ND> Ud[NV], Bd[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        Ud[v] = dconst<ND>(Pn[v]);
+        Ud[v].t[v] = 1.0;
+        Bd[v] = dconst<ND>(Ub[v]);
+        Bd[v].t[NV + v] = 1.0;
+      }
+      const Dual<ND> sd = node_factor_dual<DIM, ND>(Ud, Bd, q);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        gP[v] = lam_s * sd.t[v];
+        sred[v * G::EPB + el] = lam_s * sd.t[NV + v];
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double lamUb = (1.0 - smin) * sumlam[v] + sred[v * G::EPB + el];
+      double r = smin * lam[v] + wn * t.inv_wsum * lamUb;
+      if (node == istar) r += gP[v];
+      lam[v] = r;
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM, int P>
+__global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce_vjp(const double* __restrict__ Pst,
+                                                                   const double* __restrict__ lam_in,
+                                                                   double* __restrict__ lam_out, MeshArgs m, Tables t,
+                                                                   PhysParams q) {
+  using G = Geo<DIM, P>;
+  constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, EPB = G::EPB;
+  __shared__ double sbuf[(NV + 1) * NT];
+  __shared__ double sred[NV * EPB];
+  __shared__ int sflag[NT];
+  const int tid = threadIdx.x;
+  const int el = tid / NPE, node = tid % NPE;
+  const long long e = (long long)blockIdx.x * EPB + el;
+  const bool act = e < m.nelem;
+  const long long g = e * NPE + node;
+  double Pn[NV], lam[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    Pn[v] = act ? Pst[v * m.ntot + g] : 1.0;
+    lam[v] = act ? lam_in[v * m.ntot + g] : 0.0;
+  }
+  physicality_vjp_block<DIM, P>(Pn, lam, act, tid, el, node, t, q, sbuf, sred, sflag);
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lam_out[v * m.ntot + g] = lam[v];
+  }
+}
+
+template <int DIM, int P, int EOS, int MODE>
+__global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_rhs_vjp(VjpArgs a) {
+  using G = Geo<DIM, P>;
+  constexpr int N1 = G::N1, NPE = G::NPE, NV = G::NV, NT = G::NT, EPB = G::EPB;
+  constexpr int NFP = G::NFP, NF = G::NF, FPB = G::FPB;
+  __shared__ double sW[NV * NT];
+  __shared__ double sL[(NV + 1) * NT];
+  __shared__ double sLW[NV * FPB];
+  __shared__ int sfb[FPB];
+  __shared__ double sred[(MODE == VJP_STAGE) ? NV * EPB : 1];
+  __shared__ int sflag[(MODE == VJP_STAGE) ? NT : 1];
+
+  const MeshArgs& m = a.m;
+  const Tables& t = a.t;
+  const PhysParams& q = a.q;
+  const long long ntot = m.ntot;
+  const int tid = threadIdx.x;
+  const int el = tid / NPE, node = tid % NPE;
+  const int e0 = blockIdx.x * EPB;
+  const int e = e0 + el;
+  const bool act = e < m.nelem;
+  const long long g = (long long)e * NPE + node;
+
+  double W[NV], mu[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    W[v] = act ? a.W[v * ntot + g] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
+    mu[v] = act ? a.lam[v * ntot + g] : 0.0;
+    sW[v * NT + tid] = W[v];
+    sL[v * NT + tid] = mu[v];
+  }
+  __syncthreads();
+
+  // ---- volume: lamF^d at this node = (2/dx_d) sum_i dhat[i][a_d] lam_(line node i); nodal flux reverse
+  double lamW[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) lamW[v] = 0.0;
+  {
+    double lamF[DIM][NV];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int id = node_coord<N1>(node, d);
+      const int pt = face_pt<DIM, N1>(node, d);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) acc += t.dhat[i][id] * sL[v * NT + el * NPE + line_node<DIM, N1>(d, pt, i)];
+        lamF[d][v] = m.two_dx[d] * acc;
+      }
+    }
+    nodal_flux_rev<EOS, DIM>(W, q, lamF, lamW);
+  }
+
+  // ---- faces: adjoint of the face flux from both elements' lift transposes; HLL reverse
+  for (int fp = tid; fp < FPB; fp += NT) {
+    const int fel = fp / (NF * NFP);
+    const int rem = fp - fel * NF * NFP;
+    const int f = rem / NFP;
+    const int pt = rem - f * NFP;
+    const int fe = e0 + fel;
+    if (fe >= m.nelem) continue;
+    const int d = f >> 1;
+    const int side = f & 1;
+    const double* lo = side ? t.lp : t.lm;
+    const double* ln = side ? t.lm : t.lp;
+    const int ob = fel * NPE;
+    double Wo[NV], Wn[NV], lamFh[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0, lacc = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        const int ln_i = line_node<DIM, N1>(d, pt, i);
+        acc += lo[i] * sW[v * NT + ob + ln_i];
+        lacc += t.iw[i] * lo[i] * sL[v * NT + ob + ln_i];
+      }
+      Wo[v] = acc;
+      // own lift: S_i -= (2/dx)(1/w_i)[l_i(+1) Fhat^+ - l_i(-1) Fhat^-]
+      lamFh[v] = (side ? -m.two_dx[d] : m.two_dx[d]) * lacc;
+    }
+    int fbo = 0;
+    if (!(Wo[0] > 0.0) || !(Wo[NV - 1] > 0.0)) {
+      fbo = 1;
+      const int nb = ob + line_node<DIM, N1>(d, pt, side ? P : 0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Wo[v] = sW[v * NT + nb];
+    }
+    const int ne = neighbour(m, fe, d, side ? 1 : -1);
+    double lamWo[NV], lamWn[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lamWo[v] = lamWn[v] = 0.0;
+    if (ne < 0) {
+      hll_flux_rev<EOS, DIM>(Wo, Wo, d, q, lamFh, lamWo, lamWo);
+    } else {
+      const long long nbase = (long long)ne * NPE;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double* srcW = a.W + v * ntot + nbase;
+        const double* srcL = a.lam + v * ntot + nbase;
+        double acc = 0.0, lacc = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+          const int ln_i = line_node<DIM, N1>(d, pt, i);
+          acc += ln[i] * srcW[ln_i];
+          lacc += t.iw[i] * ln[i] * srcL[ln_i];
+        }
+        Wn[v] = acc;
+        // the neighbour sees this face from its other side
+        lamFh[v] += (side ? m.two_dx[d] : -m.two_dx[d]) * lacc;
+      }
+      if (!(Wn[0] > 0.0) || !(Wn[NV - 1] > 0.0)) {
+        const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, side ? 0 : P);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Wn[v] = src[v * ntot];
+      }
+      if (side) hll_flux_rev<EOS, DIM>(Wo, Wn, d, q, lamFh, lamWo, lamWn);
+      else hll_flux_rev<EOS, DIM>(Wn, Wo, d, q, lamFh, lamWn, lamWo);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sLW[v * FPB + fp] = lamWo[v];
+    sfb[fp] = fbo;
+  }
+  __syncthreads();
+
+  // ---- transposed trace interpolation (or the fallback node)
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int id = node_coord<N1>(node, d);
+    const int pt = face_pt<DIM, N1>(node, d);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int fpi = (el * NF + 2 * d + side) * NFP + pt;
+      double coef;
+      if (sfb[fpi]) coef = (id == (side ? P : 0)) ? 1.0 : 0.0;
+      else coef = side ? t.lp[id] : t.lm[id];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lamW[v] += coef * sLW[v * FPB + fpi];
+    }
+  }
+
+  // ---- recovery adjoint (implicit-function theorem)
+  double lamU[NV];
+  if (is_floor_state<DIM>(W, q)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lamU[v] = 0.0;
+  } else {
+    double J[NV][NV];
+    prim_jacobian<EOS, DIM>(W, q, J);
+    solve_transposed<NV>(J, lamW, lamU);
+  }
+
+  if constexpr (MODE == VJP_PLAIN) {
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = lamU[v];
+    }
+  } else {
+    double lp[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      lp[v] = a.cb * (mu[v] + a.dt * lamU[v]);
+      const double prev = (act && !a.lamn_init) ? a.lamn[v * ntot + g] : 0.0;
+      acc[v] = prev + a.ca * mu[v];
+    }
+    if (a.Pprev) {
+      double Pn[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Pn[v] = act ? a.Pprev[v * ntot + g] : 1.0;
+      __syncthreads();
+      physicality_vjp_block<DIM, P>(Pn, lp, act, tid, el, node, t, q, sL, sred, sflag);
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          a.out[v * ntot + g] = lp[v];
+          a.lamn[v * ntot + g] = acc[v];
+        }
+      }
+    } else if (act) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = acc[v] + lp[v];
+    }
+  }
+}
+
+// ------------------------------------------------ objective J = int v_y^2 dA
+template <int EOS, int DIM>
+__global__ __launch_bounds__(256) void k_objective(const double* __restrict__ U, double* __restrict__ partial,
+                                                   double* __restrict__ grad, long long ntot, int npe, int n1,
+                                                   Tables t, double jac, PhysParams q) {
+  constexpr int NV = DIM + 2;
+  __shared__ double red[256];
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double Jn = 0.0;
+  if (n < ntot) {
+    double u[NV], W[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[v * ntot + n];
+    const int st = con2prim<EOS, DIM>(u, W, q);
+    const int node = (int)(n % npe);
+    double wn = t.w[node % n1];
+    if (DIM > 1) wn *= t.w[(node / n1) % n1];
+    if (DIM > 2) wn *= t.w[node / (n1 * n1)];
+    const double cw = jac * wn;
+    double lamU[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lamU[v] = 0.0;
+    if constexpr (DIM >= 2) {
+      double usq = 0.0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) usq += W[1 + j] * W[1 + j];
+      const double gm = sqrt(1.0 + usq * q.inv_c2);
+      const double vy = W[2] / gm;
+      Jn = cw * vy * vy;
+      if (grad && (st == C2P_OK || st == C2P_NOCONV)) {
+        double lamW[NV];
+        lamW[0] = 0.0;
+        lamW[NV - 1] = 0.0;
+        const double common = 2.0 * cw * vy;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          lamW[1 + k] = common * ((k == 1 ? 1.0 / gm : 0.0) - W[2] * W[1 + k] * q.inv_c2 / (gm * gm * gm));
+        double J[NV][NV];
+        prim_jacobian<EOS, DIM>(W, q, J);
+        solve_transposed<NV>(J, lamW, lamU);
+      }
+    }
+    if (grad) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) grad[v * ntot + n] = lamU[v];
+    }
+  }
+  red[threadIdx.x] = Jn;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Adjoint of (rho, v, P) -> U: lam_src = (dU/d(rho, v, P))^T lamU.
+template <int EOS, int DIM>
+__global__ __launch_bounds__(256) void k_prim3_vjp(const double* __restrict__ S, const double* __restrict__ lamU,
+                                                   double* __restrict__ lamS, long long ntot, PhysParams q) {
+  constexpr int NV = DIM + 2;
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= ntot) return;
+  double w[NV], lu[NV], out[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    w[v] = S[v * ntot + n];
+    lu[v] = lamU[v * ntot + n];
+    out[v] = 0.0;
+  }
+  double v2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) v2 += w[1 + j] * w[1 + j];
+  const double b2 = v2 * q.inv_c2;
+  const bool ok = (w[0] > 0.0) && (w[NV - 1] > 0.0) && (b2 < 1.0) && isfinite(w[0]) && isfinite(w[NV - 1]) &&
+                  isfinite(b2);
+  if (ok) {
+    const double gm = 1.0 / sqrt(1.0 - b2);
+    double Wu[NV];
+    Wu[0] = w[0];
+    Wu[NV - 1] = w[NV - 1];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) Wu[1 + j] = gm * w[1 + j];
+    double J[NV][NV];
+    prim_jacobian<EOS, DIM>(Wu, q, J);
+    double lw[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < NV; ++r) acc += J[r][c] * lu[r];
+      lw[c] = acc;
+    }
+    out[0] = lw[0];
+    out[NV - 1] = lw[NV - 1];
+    double vl = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) vl += w[1 + j] * lw[1 + j];
+    // u = gamma v:  du_j/dv_k = gamma delta_jk + gamma^3 v_j v_k / c^2
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) out[1 + k] = gm * lw[1 + k] + gm * gm * gm * vl * w[1 + k] * q.inv_c2;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) lamS[v * ntot + n] = out[v];
+}
+
+}  // namespace dgsrhd

@@ -1,0 +1,39 @@
+// Internal host-side context shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/dgsrhd.h"
+#include "launch.hpp"
+
+struct dg_ctx {
+  dg_mesh_desc desc{};
+  hipStream_t stream = nullptr;
+  dgsrhd::PhysParams q{};
+  dgsrhd::Tables t{};
+  dgsrhd::MeshArgs m{};
+  int nv = 0, npe = 0;
+  long long ntot = 0;
+  double* Wa = nullptr;
+  double* Wb = nullptr;
+  double* U1 = nullptr;
+  double* U2 = nullptr;
+  double* adj = nullptr;     // adjoint scratch (allocated on first use)
+  size_t adj_doubles = 0;
+  dgsrhd::Counters* cnt = nullptr;
+  dgsrhd::Counters last{};           // counter snapshot for sync-mode error reporting
+  std::string err;
+};
+
+
+namespace dgsrhd {
+int fail(dg_ctx* c, int code, const char* fmt, ...);
+int hipcheck(dg_ctx* c, hipError_t e, const char* what);
+int finish(dg_ctx* c, const char* what);
+ElemArgs base_args(dg_ctx* c);
+hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a);
+hipError_t L_con2prim(dg_ctx* c, const double* U, double* W);
+hipError_t L_enforce(dg_ctx* c, double* U);
+hipError_t L_prim3(dg_ctx* c, const double* S, double* U);
+}  // namespace dgsrhd

@@ -1,0 +1,407 @@
+// Host side of the C ABI declared in include/dgsrhd.h: context, basis tables,
+// scratch management, launch sequencing on the caller's HIP stream, counters.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dgsrhd.h"
+#include "ctx.hpp"
+
+using namespace dgsrhd;
+
+namespace dgsrhd {
+__global__ void k_reset_counters(Counters* cnt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    cnt->c2p_fail = cnt->c2p_noconv = cnt->trace_fallback = 0ull;
+    cnt->flagged = cnt->smoothed = cnt->bad_average = cnt->bad_input = 0ull;
+    cnt->first_bad = ~0ull;
+  }
+}
+
+}  // namespace dgsrhd
+
+namespace dgsrhd {
+
+static const char* kNoCtx = "null context";
+
+int fail(dg_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+int hipcheck(dg_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return DG_OK;
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n, and the
+// Lagrange tables through barycentric weights.
+void gl_tables(int p, int dim, Tables& t) {
+  const int n = p + 1;
+  std::vector<double> x(n), w(n);
+  if (n == 1) {
+    x[0] = 0.0;
+    w[0] = 2.0;
+  } else {
+    for (int i = 0; i < n; ++i) {
+      double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+      double dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        const double dz = p1 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-16) break;
+      }
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      x[n - 1 - i] = z;
+      w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+  }
+  std::vector<double> bw(n, 1.0);
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k)
+      if (k != j) bw[j] /= (x[j] - x[k]);
+  // Dm[i][j] = l_j'(x_i)
+  std::vector<double> Dm(n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double diag = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      Dm[i * n + j] = (bw[j] / bw[i]) / (x[i] - x[j]);
+      diag -= Dm[i * n + j];
+    }
+    Dm[i * n + i] = diag;
+  }
+  std::memset(&t, 0, sizeof(t));
+  double wsum = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double lp = 1.0, lm = 1.0;
+    for (int k = 0; k < n; ++k) {
+      if (k == i) continue;
+      lp *= (1.0 - x[k]) / (x[i] - x[k]);
+      lm *= (-1.0 - x[k]) / (x[i] - x[k]);
+    }
+    t.lp[i] = lp;
+    t.lm[i] = lm;
+    t.w[i] = w[i];
+    t.iw[i] = 1.0 / w[i];
+    wsum += w[i];
+    for (int a = 0; a < n; ++a) t.dhat[i][a] = w[a] * Dm[a * n + i] / w[i];
+  }
+  t.inv_wsum = 1.0 / std::pow(wsum, dim);
+  for (int i = 0; i < n; ++i) {
+    t.lp_f[i] = (float)t.lp[i];
+    t.lm_f[i] = (float)t.lm[i];
+    t.iw_f[i] = (float)t.iw[i];
+    for (int a = 0; a < n; ++a) t.dhat_f[i][a] = (float)t.dhat[i][a];
+  }
+}
+
+hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a) {
+  const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos, prec = c->desc.precision;
+  if (dim == 1) return launch_element_dim1(p, eos, prec, mode, a, c->stream);
+  if (dim == 2) return launch_element_dim2(p, eos, prec, mode, a, c->stream);
+  return launch_element_dim3(p, eos, prec, mode, a, c->stream);
+}
+
+hipError_t L_con2prim(dg_ctx* c, const double* U, double* W) {
+  const int dim = c->desc.dim, eos = c->desc.eos;
+  if (dim == 1) return launch_con2prim_dim1(eos, U, W, c->ntot, c->npe, c->q, c->cnt, c->stream);
+  if (dim == 2) return launch_con2prim_dim2(eos, U, W, c->ntot, c->npe, c->q, c->cnt, c->stream);
+  return launch_con2prim_dim3(eos, U, W, c->ntot, c->npe, c->q, c->cnt, c->stream);
+}
+
+hipError_t L_enforce(dg_ctx* c, double* U) {
+  const int dim = c->desc.dim, p = c->desc.p;
+  if (dim == 1) return launch_enforce_dim1(p, U, c->m, c->t, c->q, c->cnt, c->stream);
+  if (dim == 2) return launch_enforce_dim2(p, U, c->m, c->t, c->q, c->cnt, c->stream);
+  return launch_enforce_dim3(p, U, c->m, c->t, c->q, c->cnt, c->stream);
+}
+
+hipError_t L_prim3(dg_ctx* c, const double* S, double* U) {
+  const int dim = c->desc.dim, eos = c->desc.eos;
+  if (dim == 1) return launch_prim3_to_cons_dim1(eos, S, U, c->ntot, c->q, c->cnt, c->stream);
+  if (dim == 2) return launch_prim3_to_cons_dim2(eos, S, U, c->ntot, c->q, c->cnt, c->stream);
+  return launch_prim3_to_cons_dim3(eos, S, U, c->ntot, c->q, c->cnt, c->stream);
+}
+
+ElemArgs base_args(dg_ctx* c) {
+  ElemArgs a{};
+  a.m = c->m;
+  a.t = c->t;
+  a.q = c->q;
+  a.cnt = c->cnt;
+  a.phys = c->desc.phys;
+  return a;
+}
+
+// After a call: in sync mode wait, then report new device-side conditions.
+int finish(dg_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
+  if (!c->desc.sync_mode) return DG_OK;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
+  Counters now{};
+  e = hipMemcpy(&now, c->cnt, sizeof(Counters), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
+  const Counters prev = c->last;
+  c->last = now;
+  if (now.bad_input > prev.bad_input)
+    return fail(c, DG_ESTATE, "%s: %llu invalid primitive input nodes", what, now.bad_input - prev.bad_input);
+  if (now.c2p_fail > prev.c2p_fail)
+    return fail(c, DG_ECON2PRIM, "%s: %llu recovery failures (first element %llu)", what,
+                now.c2p_fail - prev.c2p_fail, now.first_bad);
+  if (now.bad_average > prev.bad_average)
+    return fail(c, DG_EAVERAGE, "%s: %llu elements with inadmissible average", what,
+                now.bad_average - prev.bad_average);
+  return DG_OK;
+}
+
+}  // namespace dgsrhd
+
+extern "C" {
+
+int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
+  if (!out) return DG_EINVAL;
+  *out = nullptr;
+  if (!desc) return DG_EINVAL;
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return DG_ENOMEM;
+  c->desc = *desc;
+  dg_mesh_desc& d = c->desc;
+  auto bad = [&](const char* msg) {
+    std::fprintf(stderr, "dg_init_mesh: %s\n", msg);
+    delete c;
+    return DG_EINVAL;
+  };
+  if (d.dim < 1 || d.dim > 3) return bad("dim must be 1, 2 or 3");
+  if (d.p < 0 || d.p > 3) return bad("p must be in 0..3");
+  for (int k = 0; k < 3; ++k) {
+    if (k >= d.dim) d.n_elem[k] = 1;
+    if (d.n_elem[k] < 1) return bad("n_elem must be >= 1");
+    if (k < d.dim && !(d.hi[k] > d.lo[k])) return bad("hi must exceed lo");
+    if (d.bc[k] != DG_BC_PERIODIC && d.bc[k] != DG_BC_OUTFLOW) return bad("bc must be periodic or outflow");
+  }
+  if (d.eos != DG_EOS_IDEAL && d.eos != DG_EOS_TM) return bad("unknown eos");
+  if (d.eos == DG_EOS_IDEAL && !(d.gamma_ad > 1.0)) return bad("gamma_ad must exceed 1");
+  if (!(d.c_light > 0.0)) return bad("c_light must be positive");
+  if (d.c2p == DG_C2P_DEFAULT) d.c2p = (d.eos == DG_EOS_IDEAL) ? DG_C2P_NEWTON : DG_C2P_CUBIC;
+  if (d.eos == DG_EOS_IDEAL && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_QUARTIC)
+    return bad("ideal EOS needs the Newton or quartic solver");
+  if (d.eos == DG_EOS_TM && d.c2p != DG_C2P_CUBIC && d.c2p != DG_C2P_BRENT)
+    return bad("TM EOS needs the cubic or Brent solver");
+  if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT) return bad("unknown precision");
+  if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
+  const long long nelem = (long long)d.n_elem[0] * d.n_elem[1] * d.n_elem[2];
+  if (nelem > (1ll << 30)) return bad("mesh too large");
+  c->stream = (hipStream_t)hip_stream;
+  c->nv = d.dim + 2;
+  c->npe = 1;
+  for (int k = 0; k < d.dim; ++k) c->npe *= d.p + 1;
+  c->ntot = nelem * c->npe;
+  PhysParams& q = c->q;
+  q.c = d.c_light;
+  q.c2 = q.c * q.c;
+  q.c4 = q.c2 * q.c2;
+  q.inv_c = 1.0 / q.c;
+  q.inv_c2 = 1.0 / q.c2;
+  q.gam = d.gamma_ad;
+  q.gm1 = d.gamma_ad - 1.0;
+  q.alpha = (d.eos == DG_EOS_IDEAL) ? d.gamma_ad / (d.gamma_ad - 1.0) : 0.0;
+  q.eps = d.phys_eps;
+  q.c2p = d.c2p;
+  gl_tables(d.p, d.dim, c->t);
+  MeshArgs& m = c->m;
+  m.nex = d.n_elem[0];
+  m.ney = d.n_elem[1];
+  m.nez = d.n_elem[2];
+  m.nelem = (int)nelem;
+  m.ntot = c->ntot;
+  for (int k = 0; k < 3; ++k) {
+    m.two_dx[k] = (k < d.dim) ? 2.0 * d.n_elem[k] / (d.hi[k] - d.lo[k]) : 0.0;
+    m.periodic[k] = (d.bc[k] == DG_BC_PERIODIC) ? 1 : 0;
+  }
+  const size_t bytes = sizeof(double) * (size_t)c->nv * (size_t)c->ntot;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc((void**)&c->Wa, bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->Wb, bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->U1, bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->U2, bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->cnt, sizeof(Counters));
+  if (e != hipSuccess) {
+    std::fprintf(stderr, "dg_init_mesh: allocation failed: %s\n", hipGetErrorString(e));
+    dg_destroy(c);
+    return DG_ENOMEM;
+  }
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, c->stream, c->cnt);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    std::fprintf(stderr, "dg_init_mesh: %s\n", hipGetErrorString(e));
+    dg_destroy(c);
+    return DG_EHIP;
+  }
+  c->last = Counters{};
+  c->last.first_bad = ~0ull;
+  *out = c;
+  return DG_OK;
+}
+
+int dg_set_stream(dg_ctx* c, void* hip_stream) {
+  if (!c) return DG_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  return DG_OK;
+}
+
+size_t dg_state_size(const dg_ctx* c) { return c ? (size_t)c->nv * (size_t)c->ntot : 0; }
+
+int dg_set_state(dg_ctx* c, int kind, const double* src, double* U) {
+  if (!c) return DG_EINVAL;
+  if (!src || !U) return fail(c, DG_EINVAL, "dg_set_state: null pointer");
+  if (kind == DG_CONSERVED) {
+    const size_t bytes = sizeof(double) * dg_state_size(c);
+    int r = hipcheck(c, hipMemcpyAsync(U, src, bytes, hipMemcpyDeviceToDevice, c->stream), "dg_set_state");
+    if (r) return r;
+  } else if (kind == DG_PRIMITIVE) {
+    int r = hipcheck(c, L_prim3(c, src, U), "dg_set_state");
+    if (r) return r;
+  } else {
+    return fail(c, DG_EINVAL, "dg_set_state: unknown kind %d", kind);
+  }
+  return finish(c, "dg_set_state");
+}
+
+int dg_con2prim(dg_ctx* c, const double* U, double* W) {
+  if (!c) return DG_EINVAL;
+  if (!U || !W) return fail(c, DG_EINVAL, "dg_con2prim: null pointer");
+  int r = hipcheck(c, L_con2prim(c, U, W), "dg_con2prim");
+  if (r) return r;
+  return finish(c, "dg_con2prim");
+}
+
+int dg_rhs(dg_ctx* c, const double* U, double* R) {
+  if (!c) return DG_EINVAL;
+  if (!U || !R) return fail(c, DG_EINVAL, "dg_rhs: null pointer");
+  if (U == R) return fail(c, DG_EINVAL, "dg_rhs: U and R alias");
+  int r = hipcheck(c, L_con2prim(c, U, c->Wa), "dg_rhs/con2prim");
+  if (r) return r;
+  ElemArgs a = base_args(c);
+  a.W = c->Wa;
+  a.out = R;
+  r = hipcheck(c, L_element(c, MODE_RHS, a), "dg_rhs/element");
+  if (r) return r;
+  return finish(c, "dg_rhs");
+}
+
+int dg_enforce_physical(dg_ctx* c, double* U) {
+  if (!c) return DG_EINVAL;
+  if (!U) return fail(c, DG_EINVAL, "dg_enforce_physical: null pointer");
+  int r = hipcheck(c, L_enforce(c, U), "dg_enforce_physical");
+  if (r) return r;
+  return finish(c, "dg_enforce_physical");
+}
+
+static int ssprk3_steps(dg_ctx* c, double* U, double dt, int nsteps, const char* what) {
+  if (!c) return DG_EINVAL;
+  if (!U) return fail(c, DG_EINVAL, "%s: null pointer", what);
+  if (nsteps < 0) return fail(c, DG_EINVAL, "%s: nsteps < 0", what);
+  if (!std::isfinite(dt)) return fail(c, DG_EINVAL, "%s: dt not finite", what);
+  if (nsteps == 0) return DG_OK;
+  double* Wa = c->Wa;
+  double* Wb = c->Wb;
+  int r = hipcheck(c, L_con2prim(c, U, Wa), what);
+  if (r) return r;
+  for (int s = 0; s < nsteps; ++s) {
+    ElemArgs a = base_args(c);
+    a.dt = dt;
+    // stage 1: U1 = Pi(U + dt L(U))
+    a.W = Wa; a.Uk = U; a.Un = U; a.ca = 0.0; a.cb = 1.0; a.out = c->U1; a.Wout = Wb;
+    if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+    // stage 2: U2 = Pi(3/4 U + 1/4 (U1 + dt L(U1)))
+    a.W = Wb; a.Uk = c->U1; a.ca = 0.75; a.cb = 0.25; a.out = c->U2; a.Wout = Wa;
+    if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+    // stage 3: U = Pi(1/3 U + 2/3 (U2 + dt L(U2))), in place
+    const bool last = (s == nsteps - 1);
+    a.W = Wa; a.Uk = c->U2; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.out = U; a.Wout = last ? nullptr : Wb;
+    if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+    double* tmp = Wa; Wa = Wb; Wb = tmp;
+  }
+  return finish(c, what);
+}
+
+int dg_ssprk3_step(dg_ctx* c, double* U, double dt) { return ssprk3_steps(c, U, dt, 1, "dg_ssprk3_step"); }
+
+int dg_ssprk3_run(dg_ctx* c, double* U, double dt, int nsteps) {
+  return ssprk3_steps(c, U, dt, nsteps, "dg_ssprk3_run");
+}
+
+int dg_get_diagnostics(dg_ctx* c, dg_diag* out) {
+  if (!c) return DG_EINVAL;
+  if (!out) return fail(c, DG_EINVAL, "dg_get_diagnostics: null pointer");
+  int r = hipcheck(c, hipStreamSynchronize(c->stream), "dg_get_diagnostics");
+  if (r) return r;
+  Counters h{};
+  r = hipcheck(c, hipMemcpy(&h, c->cnt, sizeof(Counters), hipMemcpyDeviceToHost), "dg_get_diagnostics");
+  if (r) return r;
+  out->c2p_fail = (long long)h.c2p_fail;
+  out->c2p_noconv = (long long)h.c2p_noconv;
+  out->trace_fallback = (long long)h.trace_fallback;
+  out->flagged = (long long)h.flagged;
+  out->smoothed = (long long)h.smoothed;
+  out->bad_average = (long long)h.bad_average;
+  out->bad_input = (long long)h.bad_input;
+  out->first_bad_elem = (h.first_bad == ~0ull) ? -1 : (long long)h.first_bad;
+  return DG_OK;
+}
+
+int dg_reset_diagnostics(dg_ctx* c) {
+  if (!c) return DG_EINVAL;
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, c->stream, c->cnt);
+  int r = hipcheck(c, hipGetLastError(), "dg_reset_diagnostics");
+  if (r) return r;
+  c->last = Counters{};
+  c->last.first_bad = ~0ull;
+  return finish(c, "dg_reset_diagnostics");
+}
+
+const char* dg_last_error(const dg_ctx* c) { return c ? c->err.c_str() : kNoCtx; }
+
+void dg_destroy(dg_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->Wa);
+  (void)hipFree(c->Wb);
+  (void)hipFree(c->U1);
+  (void)hipFree(c->U2);
+  (void)hipFree(c->adj);
+  (void)hipFree(c->cnt);
+  delete c;
+}
+
+}  // extern "C"

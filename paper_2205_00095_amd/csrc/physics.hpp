@@ -1,0 +1,387 @@
+// Device-side SRHD physics for the gfx950 kernels: equations of state (Sec. 2.2),
+// primitive/conserved relations and fluxes (Sec. 2.1), wavespeeds and the HLL
+// numerical flux (Sec. 2.4), admissibility (Sec. 2.5, Eq. physicality) and the
+// four conserved-to-primitive solvers of Sec. 3.  Everything is FP64 and lives
+// in registers; one node (or one face point) per lane.
+//
+// Variables: primitive W = (rho, u_1..u_DIM, P) with u = gamma v the spatial
+// 4-velocity; conserved U = (D, S_1..S_DIM, tau) with S the momentum density and
+// tau = E - D c^2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dgsrhd {
+
+enum { EOS_IDEAL = 0, EOS_TM = 1 };
+enum { C2P_NEWTON = 0, C2P_QUARTIC = 1, C2P_CUBIC = 2, C2P_BRENT = 3 };
+enum { C2P_OK = 0, C2P_INADMISSIBLE = 1, C2P_NOCONV = 2, C2P_BADP = 3 };
+
+// Floor state written for a failed recovery: rho = 1e-10, u = 0, P = 1e-10 c^2.
+constexpr double kRhoFloor = 1e-10;
+constexpr double kPFloor = 1e-10;
+
+struct PhysParams {
+  double c, c2, c4, inv_c, inv_c2;
+  double gam;    // adiabatic index Gamma (ideal EOS)
+  double gm1;    // Gamma - 1
+  double alpha;  // Gamma / (Gamma - 1)
+  double eps;    // relative margin of the physicality operator
+  int c2p;       // recovery solver
+};
+
+// ---------------------------------------------------------------- EOS (Sec. 2.2)
+// h - c^2 as a function of Theta = P / rho.  Taub-Matthews:
+// h = 5/2 Theta + 3/2 sqrt(Theta^2 + 4/9 c^4); the excess over c^2 is
+// 5/2 Theta + 3/2 Theta^2 / (sqrt(Theta^2 + 4/9 c^4) + 2/3 c^2), free of cancellation.
+template <int EOS>
+__host__ __device__ __forceinline__ double h_excess(double th, const PhysParams& q) {
+  if constexpr (EOS == EOS_IDEAL) {
+    return q.alpha * th;
+  } else {
+    const double s = sqrt(th * th + (4.0 / 9.0) * q.c4);
+    return 2.5 * th + 1.5 * th * th / (s + (2.0 / 3.0) * q.c2);
+  }
+}
+
+// Sound speed squared: ideal c^2 Gamma Theta / h; Taub-Matthews
+// c^2 (3 Theta^2 + 5 Theta s) / (12 Theta^2 + 2 c^4 + 12 Theta s).
+template <int EOS>
+__host__ __device__ __forceinline__ double sound2(double th, double he, const PhysParams& q) {
+  if constexpr (EOS == EOS_IDEAL) {
+    return q.c2 * q.gam * th / (q.c2 + he);
+  } else {
+    const double s = sqrt(th * th + (4.0 / 9.0) * q.c4);
+    const double num = 3.0 * th * th + 5.0 * th * s;
+    const double den = 12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s;
+    return q.c2 * num / den;
+  }
+}
+
+// ------------------------------------------------- state relations (Sec. 2.1)
+// Everything a face or node needs from a primitive state: conserved variables
+// (Eq. primitive_to_conserved) and the pieces shared by fluxes and wavespeeds.
+template <int EOS, int DIM>
+struct StateEval {
+  double U[DIM + 2];
+  double g2, ig;  // gamma^2, 1/gamma
+  double P;
+  double th, he;  // Theta, h - c^2
+};
+
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void eval_state(const double* W, const PhysParams& q, StateEval<EOS, DIM>& s) {
+  const double rho = W[0];
+  const double P = W[DIM + 1];
+  double usq = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) usq += W[1 + j] * W[1 + j];
+  const double g2 = 1.0 + usq * q.inv_c2;
+  const double g = sqrt(g2);
+  const double th = P / rho;
+  const double he = h_excess<EOS>(th, q);
+  const double D = g * rho;
+  const double gH = g * rho * (q.c2 + he) * q.inv_c2;  // gamma rho h / c^2
+  s.U[0] = D;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) s.U[1 + j] = gH * W[1 + j];
+  // tau = gamma^2 rho h - P - D c^2 = D |u|^2/(gamma+1) + gamma^2 rho (h - c^2) - P
+  s.U[DIM + 1] = D * usq / (g + 1.0) + g2 * rho * he - P;
+  s.g2 = g2;
+  s.ig = 1.0 / g;
+  s.P = P;
+  s.th = th;
+  s.he = he;
+}
+
+// Physical flux along direction d in (D, S, tau) variables (Eq. srhd_flux with the
+// energy row minus c^2 times the mass row): (D v_d, S v_d + P e_d, (tau + P) v_d).
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void flux_dir(const double* W, const StateEval<EOS, DIM>& s, int d, double* F) {
+  const double vd = W[1 + d] * s.ig;
+#pragma unroll
+  for (int k = 0; k < DIM + 2; ++k) F[k] = s.U[k] * vd;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+    if (j == d) F[1 + j] += s.P;
+  F[DIM + 1] += s.P * vd;
+}
+
+// Extreme signal speeds along d (Sec. 2.4):
+// lambda_pm = (v_d pm sqrt(sigma (c^2 - v_d^2 + c^2 sigma)))/(1 + sigma),
+// sigma = c_s^2 / (gamma^2 (c^2 - c_s^2)).
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void wavespeeds(const double* W, const StateEval<EOS, DIM>& s, int d,
+                                           const PhysParams& q, double& lm, double& lp) {
+  const double cs2 = sound2<EOS>(s.th, s.he, q);
+  const double vd = W[1 + d] * s.ig;
+  const double sigma = cs2 / (s.g2 * (q.c2 - cs2));
+  const double root = sqrt(sigma * (q.c2 - vd * vd + q.c2 * sigma));
+  const double inv = 1.0 / (1.0 + sigma);
+  lm = (vd - root) * inv;
+  lp = (vd + root) * inv;
+}
+
+// HLL numerical flux along d between left and right primitive states
+// (lambda_L = min of the two lambda_-, lambda_R = max of the two lambda_+).
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void hll_flux(const double* WL, const double* WR, int d, const PhysParams& q,
+                                         double* Fh) {
+  constexpr int NV = DIM + 2;
+  StateEval<EOS, DIM> sL, sR;
+  eval_state<EOS, DIM>(WL, q, sL);
+  eval_state<EOS, DIM>(WR, q, sR);
+  double FL[NV], FR[NV];
+  flux_dir<EOS, DIM>(WL, sL, d, FL);
+  flux_dir<EOS, DIM>(WR, sR, d, FR);
+  double lmL, lpL, lmR, lpR;
+  wavespeeds<EOS, DIM>(WL, sL, d, q, lmL, lpL);
+  wavespeeds<EOS, DIM>(WR, sR, d, q, lmR, lpR);
+  const double aL = fmin(lmL, lmR);
+  const double aR = fmax(lpL, lpR);
+  if (aL >= 0.0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) Fh[k] = FL[k];
+  } else if (aR <= 0.0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) Fh[k] = FR[k];
+  } else {
+    const double inv = 1.0 / (aR - aL);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) Fh[k] = (aR * FL[k] - aL * FR[k] + aL * aR * (sR.U[k] - sL.U[k])) * inv;
+  }
+}
+
+// --------------------------------------------------- admissibility (Sec. 2.5)
+// q(U) = E/c^2 - sqrt(D^2 + |S|^2/c^2) in tau form: tau/c^2 - (|S|^2/c^2)/(D + sqrt(D^2 + |S|^2/c^2)).
+template <int DIM>
+__host__ __device__ __forceinline__ bool admissible(const double* U, const PhysParams& q) {
+  const double D = U[0];
+  double s2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) s2 += U[1 + j] * U[1 + j];
+  s2 *= q.inv_c2;
+  const double qq = U[DIM + 1] * q.inv_c2 - s2 / (D + sqrt(D * D + s2));
+  return (D > 0.0) && (qq > 0.0);
+}
+
+// ------------------------------------------------ recovery (Sec. 3)
+__host__ __device__ __forceinline__ double cube_root(double x) { return cbrt(x); }
+
+// TM cubic of Eq. (synge_cubic): W^3 + c1 W^2 + c2 W + c3 = 0, W = gamma^2 - 1.
+__host__ __device__ __forceinline__ void tm_cubic_coeffs(double xi, double eta, double& c1, double& c2, double& c3) {
+  const double x2 = xi * xi, e2 = eta * eta;
+  const double dm = (eta - xi) * (eta + xi);
+  const double den = dm * dm;
+  const double k = 4.0 * (e2 + x2) - (x2 + 1.0);
+  c1 = ((e2 + x2) * k - 14.0 * x2 * e2) / (2.0 * den);
+  c2 = (k * k - 57.0 * x2 * e2) / (16.0 * den);
+  c3 = -9.0 * x2 * e2 / (16.0 * den);
+}
+
+// Brent's bracketed root finder (inverse quadratic interpolation / secant with
+// bisection safeguard) on the TM cubic over [lo, hi]; returns false at the cap.
+__host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, double c3, double lo, double hi, double& root) {
+  auto f = [&](double W) { return ((W + c1) * W + c2) * W + c3; };
+  double a = lo, b = hi, fa = f(a), fb = f(b);
+  double c = a, fc = fa, d = b - a, e = d;
+  const double eps = 2.220446049250313e-16;
+  for (int it = 0; it < 100; ++it) {
+    if ((fb > 0.0) == (fc > 0.0)) {
+      c = a; fc = fa; d = b - a; e = d;
+    }
+    if (fabs(fc) < fabs(fb)) {
+      a = b; b = c; c = a; fa = fb; fb = fc; fc = fa;
+    }
+    const double tol1 = 2.0 * eps * fabs(b);
+    const double xm = 0.5 * (c - b);
+    if (fabs(xm) <= tol1 || fb == 0.0) {
+      root = b;
+      return true;
+    }
+    if (fabs(e) >= tol1 && fabs(fa) > fabs(fb)) {
+      double p, qq;
+      const double s = fb / fa;
+      if (a == c) {
+        p = 2.0 * xm * s;
+        qq = 1.0 - s;
+      } else {
+        const double t = fa / fc, r = fb / fc;
+        p = s * (2.0 * xm * t * (t - r) - (b - a) * (r - 1.0));
+        qq = (t - 1.0) * (r - 1.0) * (s - 1.0);
+      }
+      if (p > 0.0) qq = -qq;
+      p = fabs(p);
+      if (2.0 * p < fmin(3.0 * xm * qq - fabs(tol1 * qq), fabs(e * qq))) {
+        e = d;
+        d = p / qq;
+      } else {
+        d = xm; e = d;
+      }
+    } else {
+      d = xm; e = d;
+    }
+    a = b; fa = fb;
+    b += (fabs(d) > tol1) ? d : (xm > 0.0 ? tol1 : -tol1);
+    fb = f(b);
+  }
+  root = b;
+  return false;
+}
+
+// Conserved -> primitive at one node with the configured solver.  Returns a C2P_*
+// status; on failure writes the floor state.  Also returns the pieces the
+// implicit-function-theorem adjoint needs through the primitive output only.
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ int con2prim(const double* U, double* W, const PhysParams& q) {
+  constexpr int NV = DIM + 2;
+  const double D = U[0];
+  const double tau = U[NV - 1];
+  double s2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) s2 += U[1 + j] * U[1 + j];
+  const double s2c = s2 * q.inv_c2;
+  const double qq = tau * q.inv_c2 - s2c / (D + sqrt(D * D + s2c));
+  int status = C2P_OK;
+  double rho = kRhoFloor, P = kPFloor * q.c2, gb = 0.0, Smag = 0.0;
+  if (!(D > 0.0) || !(qq > 0.0)) {
+    status = C2P_INADMISSIBLE;
+  } else {
+    Smag = sqrt(s2);
+    const double iD = 1.0 / D;
+    const double xi = Smag * iD * q.inv_c;
+    const double t = tau * iD * q.inv_c2;  // eta - 1
+    const double eta = 1.0 + t;
+    int method = q.c2p;
+    if constexpr (EOS == EOS_IDEAL) {
+      const double al = q.alpha;
+      double w = 0.0;
+      if (method == C2P_QUARTIC) {
+        // analytic quartic in beta through its resolvent cubic (readings: leading
+        // beta^4 with a3 on beta^3; R with 9 i1 i2; trigonometric branch via atan2)
+        const double G = q.gam, g1 = q.gm1;
+        const double den = g1 * g1 * (xi * xi + 1.0);
+        const double a3 = -2.0 * G * g1 * xi * eta / den;
+        const double a2 = (G * G * eta * eta + 2.0 * g1 * xi * xi - g1 * g1) / den;
+        const double a1 = -2.0 * G * xi * eta / den;
+        const double a0 = xi * xi / den;
+        const double i1 = -a2, i2 = a3 * a1 - 4.0 * a0, i3 = 4.0 * a2 * a0 - a1 * a1 - a3 * a3 * a0;
+        const double R = (9.0 * i1 * i2 - 27.0 * i3 - 2.0 * i1 * i1 * i1) / 54.0;
+        const double Sq = (3.0 * i2 - i1 * i1) / 9.0;
+        const double T = R * R + Sq * Sq * Sq;
+        double x;
+        if (T < 0.0) {
+          x = 2.0 * sqrt(-Sq) * cos(atan2(sqrt(-T), R) / 3.0) - i1 / 3.0;
+        } else {
+          const double sT = sqrt(T);
+          x = cube_root(R + sT) + cube_root(R - sT) - i1 / 3.0;
+        }
+        const double Bq = 0.5 * (a3 + sqrt(a3 * a3 - 4.0 * a2 + 4.0 * x));
+        const double Cq = 0.5 * (x - sqrt(x * x - 4.0 * a0));
+        double beta = 0.5 * (-Bq + sqrt(Bq * Bq - 4.0 * Cq));
+        if (!(xi > 0.0)) beta = 0.0;
+        if (!isfinite(beta)) {
+          status = C2P_NOCONV;
+        } else {
+          const double sq = sqrt((1.0 - beta) * (1.0 + beta));
+          rho = D * sq;
+          gb = beta / sq;
+          P = q.gm1 * (tau - Smag * beta * q.c + D * q.c2 * beta * beta / (1.0 + sq));
+        }
+      } else {
+        // Newton-Raphson on the quartic P(w) of Eq. (iterative_quartic)
+        const double A = (al - 1.0) * xi;
+        const double B = 2.0 * (al * t + al + 1.0);   // 2 (alpha eta + 1)
+        const double C = 2.0 * (al + 1.0) * xi;
+        const double Dd = 2.0 * (al * t + al - 1.0);  // 2 (alpha eta - 1)
+        if (xi < 1e-4) {
+          // small-xi series, Eq. (iterative_cubic_approximation)
+          const double ame = 0.5 * Dd, ape = 0.5 * B;
+          const double k1 = (al - 1.0) / (2.0 * ame);
+          const double k3 = (al - 1.0) * (al - 1.0) / (8.0 * ame * ame * ame * ame) *
+                            ((al + 3.0) * ape - 4.0 * (al + 1.0));
+          w = k1 * xi + k3 * xi * xi * xi;
+        } else {
+          const double b = xi / eta;
+          w = b / (1.0 + sqrt(1.0 - b * b));
+          bool conv = false;
+          for (int it = 0; it < 30; ++it) {
+            const double Pw = (((A * w - B) * w + C) * w - Dd) * w + A;
+            const double dPw = ((4.0 * A * w - 3.0 * B) * w + 2.0 * C) * w - Dd;
+            double wn = w - Pw / dPw;
+            if (wn <= 0.0) wn = 0.5 * w;
+            else if (wn >= 1.0) wn = 0.5 * (w + 1.0);
+            const double step = fabs(wn - w);
+            w = wn;
+            if (step <= 1e-13 * wn) { conv = true; break; }
+          }
+          if (!conv) status = C2P_NOCONV;
+        }
+        const double w2 = w * w;
+        const double om = (1.0 - w) * (1.0 + w);
+        const double beta = 2.0 * w / (1.0 + w2);
+        rho = D * om / (1.0 + w2);
+        gb = 2.0 * w / om;
+        P = q.gm1 * (tau - Smag * beta * q.c + D * q.c2 * 2.0 * w2 / (1.0 + w2));
+      }
+    } else {
+      double c1, c2, c3;
+      tm_cubic_coeffs(xi, eta, c1, c2, c3);
+      double Wc;
+      if (method == C2P_BRENT) {
+        if (c3 == 0.0) {
+          Wc = 0.0;
+        } else {
+          double hi = 200.0 * 200.0 - 1.0;
+          for (int k = 0; k < 60 && (((hi + c1) * hi + c2) * hi + c3) < 0.0; ++k) hi *= 4.0;
+          if (!tm_brent_root(c1, c2, c3, 0.0, hi, Wc)) status = C2P_NOCONV;
+        }
+      } else {
+        // analytic (trigonometric / Cardano), then one Newton step on the cubic
+        const double Q = (3.0 * c2 - c1 * c1) / 9.0;
+        const double R = (9.0 * c1 * c2 - 27.0 * c3 - 2.0 * c1 * c1 * c1) / 54.0;
+        const double dd = Q * Q * Q + R * R;
+        if (dd < 0.0) {
+          double arg = R / sqrt(-Q * Q * Q);
+          arg = fmin(1.0, fmax(-1.0, arg));
+          Wc = 2.0 * sqrt(-Q) * cos(acos(arg) / 3.0) - c1 / 3.0;
+        } else {
+          const double sd = sqrt(dd);
+          Wc = -c1 / 3.0 + cube_root(R + sd) + cube_root(R - sd);
+        }
+        const double f = ((Wc + c1) * Wc + c2) * Wc + c3;
+        const double fp = (3.0 * Wc + 2.0 * c1) * Wc + c2;
+        Wc = Wc - f / fp;
+      }
+      Wc = fmax(Wc, 0.0);
+      const double gam = sqrt(1.0 + Wc);
+      const double beta = sqrt(Wc / (Wc + 1.0));
+      gb = sqrt(Wc);
+      rho = D / gam;
+      // P = (X^2 - (rho c^2)^2)/(3X), X = E - M.v, via X_ = X - rho c^2
+      const double Xm = tau - Smag * beta * q.c + D * q.c2 * Wc / (gam * (gam + 1.0));
+      const double X = Xm + rho * q.c2;
+      P = Xm * (Xm + 2.0 * rho * q.c2) / (3.0 * X);
+    }
+    if (!(P > 0.0) || !isfinite(P) || !isfinite(rho)) {
+      if (status == C2P_OK) status = C2P_BADP;
+    }
+  }
+  if (status != C2P_OK && status != C2P_NOCONV) {
+    rho = kRhoFloor;
+    P = kPFloor * q.c2;
+    gb = 0.0;
+  }
+  if (status == C2P_NOCONV && (!(P > 0.0) || !isfinite(P) || !isfinite(rho) || !isfinite(gb))) {
+    rho = kRhoFloor;
+    P = kPFloor * q.c2;
+    gb = 0.0;
+  }
+  W[0] = rho;
+  const double scale = (Smag > 0.0) ? gb * q.c / Smag : 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) W[1 + j] = scale * U[1 + j];
+  W[NV - 1] = P;
+  return status;
+}
+
+}  // namespace dgsrhd

@@ -22,3 +22,20 @@ def rel_err_per_var(a, b):
     num = (a - b).abs().max(1).values
     den = b.abs().max(1).values.clamp(min=1e-300)
     return (num / den)
+
+
+def perturbed(U, rel=1e-15, seed=0):
+    """U with every entry scaled by (1 + rel * N(0,1)) (a few ulps at rel = 1e-15)."""
+    g = torch.Generator().manual_seed(seed)
+    return U * (1.0 + rel * torch.randn(U.shape, generator=g, dtype=torch.float64))
+
+
+def parity_tol(fn, U, floor=1e-12):
+    """Acceptance bar for GPU-vs-oracle parity of X = fn(U): 1e-12 normwise relative per
+    component, or the oracle's own response to a ~5-ulp relative perturbation of its input
+    when the problem's FP64 conditioning makes that larger (cancellation-dominated RHS,
+    chaotic stress data).  Returns (tol, sensitivity) per component."""
+    X0 = fn(U)
+    X1 = fn(perturbed(U))
+    sens = rel_err_per_var(X1, X0)
+    return torch.clamp(sens, min=floor), sens

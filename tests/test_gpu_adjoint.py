@@ -1,0 +1,213 @@
+"""GPU adjoint vs the oracle's FP64 reverse mode (torch autograd through the oracle)
+and vs central finite differences.
+
+Bars: vector-Jacobian products agree with the oracle's reverse mode to 1e-9
+normwise relative per component on smooth data (the benchmark spec asks 1e-6; the
+implicit-function-theorem and hand-reversed HLL reach rounding level); the
+trajectory gradient of J = int v_y^2 dA agrees with central differences to
+1e-6 relative per direction."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dg as odg
+from oracle import objective as oobj
+from oracle import physicality as ophys
+from oracle import srhd as osrhd
+from oracle import timestep as ots
+from oracle.setup import IDEAL, Setup
+from paper_2205_00095_amd import workloads as wl
+
+from ._util import oracle_state, perturbed, rel_err_per_var
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(cfg):
+    from paper_2205_00095_amd.solver import Solver
+    return Solver(cfg)
+
+
+def _lam(shape, seed):
+    g = torch.Generator().manual_seed(seed)
+    return torch.randn(shape, generator=g, dtype=torch.float64)
+
+
+# The ideal-gas Kelvin-Helmholtz cases use the seeded-noise initial data ("kh"):
+# without noise, left and right face states tie exactly in the HLL min/max
+# wavespeed selection, where the RHS has no derivative (the oracle's own VJP then
+# jumps by 1e-4 under 1e-15 input perturbations).
+VJP_CASES = [("kh_ideal", {"n_elem": (6, 5, 1), "init": "kh"}), ("kh_tm", {"n_elem": (5, 4, 1)}),
+             ("wave1d", {"n_elem": (20, 1, 1)}), ("kh_ideal", {"n_elem": (5, 4, 1), "p": 1, "init": "kh"}),
+             ("random3d", {"n_elem": (3, 2, 2), "p": 1}), ("kh_tm", {"n_elem": (4, 4, 1), "p": 0}),
+             ("kh_ideal", {"n_elem": (6, 5, 1), "p": 3, "init": "kh"})]
+
+
+def _vjp_ref(st, U, lamR):
+    Ur = U.clone().requires_grad_(True)
+    return torch.autograd.grad(odg.rhs(Ur, st), Ur, lamR)[0]
+
+
+@pytest.mark.parametrize("kind,over", VJP_CASES)
+def test_rhs_vjp_matches_oracle_autograd(kind, over):
+    cfg = wl.make_config(kind, precision=wl.FP64, **over)
+    st, U = oracle_state(cfg)
+    lamR = _lam(U.shape, 7)
+    ref = _vjp_ref(st, U, lamR)
+    sens = rel_err_per_var(_vjp_ref(st, perturbed(U), lamR), ref)
+    assert float(sens.max()) < 1e-10, f"test data sits on a derivative kink: {sens.tolist()}"
+    got = _solver(cfg).rhs_vjp(U.cuda(), lamR.cuda()).cpu()
+    err = rel_err_per_var(got, ref)
+    print(f"{kind} {over}: rhs_vjp err {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9, err.tolist()
+
+
+def test_rhs_vjp_dot_product_with_fd():
+    """<lamR, (R(U + h dU) - R(U - h dU))/2h> = <VJP(lamR), dU> on the GPU alone, on a
+    field of i.i.d. moderate random states (face states differ by O(1), so no HLL
+    wavespeed near-ties), best of a step sweep h = 1e-4 .. 1e-7."""
+    cfg = wl.make_config("kh_ideal", n_elem=(8, 7, 1), p=1, bc=(0, 0, 0))
+    st = Setup.from_config(cfg)
+    rng = np.random.default_rng(12)
+    shape = wl.field_shape(cfg)
+    rho, P = rng.uniform(0.8, 1.2, shape), rng.uniform(0.8, 1.2, shape)
+    v = rng.uniform(-0.3, 0.3, (2,) + shape)
+    U = osrhd.prim3_to_cons(*(torch.from_numpy(a) for a in (rho, v, P)), st).contiguous()
+    s = _solver(cfg)
+    Ud = U.cuda()
+    dU = _lam(U.shape, 3).cuda() * Ud.abs()
+    lamR = _lam(U.shape, 4).cuda()
+    rhs = float((s.rhs_vjp(Ud, lamR) * dU).sum())
+    errs = []
+    for h in (1e-4, 1e-5, 1e-6, 1e-7):
+        Rp = s.rhs((Ud + h * dU).contiguous())
+        Rm = s.rhs((Ud - h * dU).contiguous())
+        lhs = float((lamR * (Rp - Rm)).sum()) / (2 * h)
+        errs.append(abs(lhs - rhs) / abs(rhs))
+    print(f"dot-product FD relative errors over the step sweep: {errs}", flush=True)
+    assert min(errs) <= 1e-8, errs
+
+
+@pytest.mark.parametrize("kind,over", [("kh_ideal", {"n_elem": (6, 5, 1)}), ("kh_tm", {"n_elem": (5, 4, 1)})])
+def test_objective_and_gradient(kind, over):
+    cfg = wl.make_config(kind, **over)
+    st, U = oracle_state(cfg)
+    Ur = U.clone().requires_grad_(True)
+    Jref = oobj.vy2_integral(Ur, st)
+    (gref,) = torch.autograd.grad(Jref, Ur)
+    J, g = _solver(cfg).objective_vy2(U.cuda(), grad=True)
+    assert abs(J - float(Jref)) <= 1e-13 * abs(float(Jref))
+    err = rel_err_per_var(g.cpu(), gref)
+    assert float(err.max()) <= 1e-9, err.tolist()
+
+
+def test_set_state_vjp_matches_autograd():
+    cfg = wl.make_config("random3d", n_elem=(3, 3, 2))
+    st = Setup.from_config(cfg)
+    rho, v, P = (torch.from_numpy(a) for a in wl.initial_primitives(cfg))
+    src = torch.cat([rho[None], v, P[None]], 0).contiguous()
+    lamU = _lam(src.shape, 9)
+    s_r = src.clone().requires_grad_(True)
+    U = osrhd.prim3_to_cons(s_r[0], s_r[1:4], s_r[4], st)
+    (ref,) = torch.autograd.grad(U, s_r, lamU)
+    got = _solver(cfg).set_state_vjp(src.cuda(), lamU.cuda()).cpu()
+    assert float(rel_err_per_var(got, ref).max()) <= 1e-11
+
+
+@pytest.mark.parametrize("kind,over", [("kh_ideal", {"n_elem": (6, 5, 1), "init": "kh"}),
+                                       ("kh_tm", {"n_elem": (4, 4, 1)})])
+def test_step_vjp_matches_oracle_autograd(kind, over):
+    cfg = wl.make_config(kind, precision=wl.FP64, **over)
+    st, U = oracle_state(cfg)
+    lam = _lam(U.shape, 11)
+    Ur = U.clone().requires_grad_(True)
+    (ref,) = torch.autograd.grad(ots.step(Ur, cfg["dt"], st), Ur, lam)
+    got = _solver(cfg).step_vjp(U.cuda(), cfg["dt"], lam.cuda()).cpu()
+    err = rel_err_per_var(got, ref)
+    print(f"{kind}: step_vjp err {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9, err.tolist()
+
+
+def test_enforce_active_branch_vjp_matches_autograd():
+    """A step whose stages trigger the physicality operator: the active-branch adjoint
+    equals autograd through the oracle's operator."""
+    from .test_gpu_parity import _flagged_mesh
+    st, U = _flagged_mesh(2, 2, (5, 4, 1), 77)
+    cfg = dict(dim=2, p=2, n_elem=(5, 4, 1), lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 0), eos=IDEAL,
+               gamma_ad=4 / 3, c=1.0, c2p=-1, precision=0, phys=True)
+    # a pre-operator state P: apply the operator's adjoint through a zero-dt step is not possible,
+    # so compare the operator alone via a step of size 0 (stages reduce to U -> Pi(U))
+    lam = _lam(U.shape, 13)
+    Ur = U.clone().requires_grad_(True)
+    out = ophys.enforce(Ur, st)
+    out = ophys.enforce(0.75 * Ur + 0.25 * out, st)
+    out = ophys.enforce(Ur / 3.0 + (2.0 / 3.0) * out, st)
+    (ref,) = torch.autograd.grad(out, Ur, lam)
+    got = _solver(cfg).step_vjp(U.cuda().contiguous(), 0.0, lam.cuda()).cpu()
+    err = rel_err_per_var(got, ref)
+    print(f"operator adjoint err {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9, err.tolist()
+
+
+def test_trajectory_gradient_matches_oracle():
+    """dJ/d(v_y perturbation) through 4 steps (checkpoint every 3) vs the oracle's reverse mode."""
+    from paper_2205_00095_amd.adjoint import vy2_after
+    cfg = wl.make_config("kh_ideal", n_elem=(4, 4, 1))
+    st = Setup.from_config(cfg)
+    rho, v, P = wl.initial_primitives(cfg)
+    delta = wl.kh_perturbation(cfg)
+    v = v.copy()
+    v[1] += delta
+    src = torch.from_numpy(wl.pack_primitives(rho, v, P))
+    dt = cfg["dt"] * 10
+    s_r = src.clone().requires_grad_(True)
+    U = osrhd.prim3_to_cons(s_r[0], s_r[1:3], s_r[3], st)
+    Jref = oobj.vy2_integral(ots.run(U, dt, 4, st), st)
+    (gref,) = torch.autograd.grad(Jref, s_r)
+    sd = src.cuda().requires_grad_(True)
+    J = vy2_after(_solver(cfg), sd, 4, dt, k=3)
+    J.backward()
+    assert abs(float(J) - float(Jref)) <= 1e-12 * abs(float(Jref))
+    err = rel_err_per_var(sd.grad.cpu()[2:3], gref[2:3])
+    print(f"trajectory gradient err (v_y) {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9
+
+
+def test_trajectory_gradient_fd_kh_adjoint_workload():
+    """The adjoint workload (128x128 p=2 ideal KH, 200 steps, checkpoint every 20):
+    gradient w.r.t. the initial v_y perturbation vs central differences on 16 seeded
+    unit directions."""
+    from paper_2205_00095_amd.adjoint import vy2_after
+    cfg = wl.make_config("kh_ideal")
+    rho, v, P = wl.initial_primitives(cfg)
+    delta = wl.kh_perturbation(cfg)
+    base = torch.from_numpy(wl.pack_primitives(rho, v, P)).cuda()
+    s = _solver(cfg)
+    nsteps, dt = cfg["steps"], cfg["dt"]
+
+    def J_of(dl):
+        src = base.clone()
+        src[2] += dl
+        with torch.no_grad():
+            return float(vy2_after(s, src, nsteps, dt))
+
+    d0 = torch.from_numpy(delta).cuda()
+    src = base.clone()
+    src[2] += d0
+    src.requires_grad_(True)
+    J = vy2_after(s, src, nsteps, dt, k=20)
+    J.backward()
+    g = src.grad[2]
+    dirs = torch.from_numpy(wl.random_directions(cfg, 16)).cuda()
+    worst = 0.0
+    for k in range(16):
+        ad = float((g * dirs[k]).sum())
+        errs = []
+        for hr in (1e-5, 1e-6, 1e-7):
+            h = hr * float(d0.norm())
+            fd = (J_of(d0 + h * dirs[k]) - J_of(d0 - h * dirs[k])) / (2 * h)
+            errs.append(abs(fd - ad) / abs(ad))
+        print(f"direction {k}: FD relative errors (h = 1e-5, 1e-6, 1e-7 |delta|) {errs}", flush=True)
+        worst = max(worst, min(errs))
+    print(f"KH adjoint workload: max over 16 directions of the best-step FD error {worst:.3e}", flush=True)
+    assert worst <= 1e-6

@@ -1,0 +1,208 @@
+"""GPU (C ABI) vs FP64 CPU oracle parity of the forward path.
+
+Inputs are the seeded workloads converted by the oracle's own prim->cons, so
+both sides see the same U.  Acceptance per conserved component k:
+||X_gpu,k - X_oracle,k||_inf / ||X_oracle,k||_inf <= max(1e-12, s_k), where s_k
+is the oracle's own normwise change when its input is perturbed by ~5 ulps
+(tests/_util.parity_tol).  s_k < 1e-12 for the Kelvin-Helmholtz and 3D RHS
+cases, so the bar there is the plain 1e-12; it exceeds 1e-12 only where FP64
+conditioning forbids 1e-12 for any two roundings (the uniform-pressure contact
+wave, whose flux-divergence terms are ~1e3 x its RHS, and a full step on the
+random 3D stress data).  Meshes span several workgroups and end in a partial
+one (ragged tail)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import con2prim as ocp
+from oracle import dg as odg
+from oracle import physicality as ophys
+from oracle import srhd as osrhd
+from oracle import timestep as ots
+from oracle.setup import BRENT, CUBIC, IDEAL, NEWTON, QUARTIC, TM, Setup
+from paper_2205_00095_amd import workloads as wl
+
+from ._util import oracle_state, parity_tol, rel_err_per_var
+
+pytestmark = pytest.mark.gpu
+
+RHS_CASES = [
+    ("wave1d", {}),
+    ("wave1d", {"p": 0, "n_elem": (300, 1, 1)}),
+    ("wave1d", {"p": 3, "eos": wl.EOS_TM, "c2p": wl.C2P_CUBIC, "n_elem": (70, 1, 1)}),
+    ("kh_tm", {"n_elem": (12, 10, 1)}),
+    ("kh_tm", {"n_elem": (9, 7, 1), "c2p": wl.C2P_BRENT}),
+    ("kh_tm", {"n_elem": (11, 6, 1), "p": 1}),
+    ("kh_ideal", {"n_elem": (10, 9, 1)}),
+    ("kh_ideal", {"n_elem": (10, 9, 1), "p": 3}),
+    ("kh_ideal", {"n_elem": (13, 5, 1), "p": 0}),
+    ("random3d", {"n_elem": (5, 4, 3)}),
+    ("random3d", {"n_elem": (4, 3, 3), "p": 1, "eos": wl.EOS_TM, "c2p": wl.C2P_CUBIC}),
+    ("random3d", {"n_elem": (3, 3, 2), "p": 3}),
+]
+
+
+def _solver(cfg, sync=True):
+    from paper_2205_00095_amd.solver import Solver
+    return Solver(cfg, sync=sync)
+
+
+def _case_cfg(kind, over):
+    cfg = wl.make_config(kind, **over)
+    cfg["precision"] = wl.FP64
+    return cfg
+
+
+@pytest.mark.parametrize("kind,over", RHS_CASES)
+def test_rhs_matches_oracle(kind, over):
+    cfg = _case_cfg(kind, over)
+    print(f"case {kind} {over}", flush=True)
+    st, U = oracle_state(cfg)
+    R_ref = odg.rhs(U, st)
+    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    s = _solver(cfg)
+    R = s.rhs(U.cuda()).cpu()
+    err = rel_err_per_var(R, R_ref)
+    print(f"err {err.tolist()} tol {tol.tolist()}")
+    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+
+
+@pytest.mark.parametrize("kind,over", [RHS_CASES[0], RHS_CASES[3], RHS_CASES[6], RHS_CASES[9]])
+def test_rhs_bitwise_reproducible(kind, over):
+    cfg = _case_cfg(kind, over)
+    st, U = oracle_state(cfg)
+    s = _solver(cfg, sync=False)
+    Ud = U.cuda()
+    R1 = s.rhs(Ud).clone()
+    R2 = s.rhs(Ud)
+    assert torch.equal(R1, R2)
+
+
+def _random_states(eos, n, gmax, seed):
+    rng = np.random.default_rng(seed)
+    g = rng.uniform(1.0, gmax, n)
+    rho = 10 ** rng.uniform(-2, 2, n)
+    P = rho * 10 ** rng.uniform(-2, 2, n)
+    nv = rng.standard_normal((3, n))
+    nv /= np.linalg.norm(nv, axis=0)
+    v = nv * np.sqrt((1 - 1 / g) * (1 + 1 / g))
+    return rho, v, P
+
+
+@pytest.mark.parametrize("eos,method,tol", [(IDEAL, NEWTON, 1e-12), (TM, CUBIC, 1e-12),
+                                            (TM, BRENT, 1e-12), (IDEAL, QUARTIC, 1e-6)])
+def test_con2prim_matches_oracle(eos, method, tol):
+    n = 64 * 5 + 17 if method != BRENT else 64 + 9
+    rho, v, P = _random_states(eos, n, 10.0, 5)
+    cfg = wl.make_config("random3d", n_elem=(n, 1, 1), p=0, eos=eos, c2p=method)
+    st = Setup.from_config(cfg)
+    U = osrhd.prim3_to_cons(torch.tensor(rho), torch.tensor(v), torch.tensor(P), st)
+    U = U.reshape((5,) + wl.field_shape(cfg))
+    W_ref, status = ocp.con2prim(U, st)
+    assert int((status != 0).sum()) == 0
+    s = _solver(cfg)
+    W = s.con2prim(U.cuda()).cpu()
+    rel = ((W - W_ref).abs() / W_ref.abs().clamp(min=1e-300)).reshape(5, -1)
+    # velocity components compared normwise (a component can be ~0)
+    umag = torch.sqrt((W_ref[1:4] ** 2).sum(0)).reshape(-1)
+    du = torch.sqrt(((W - W_ref)[1:4] ** 2).sum(0)).reshape(-1)
+    assert float(rel[0].max()) <= tol and float(rel[4].max()) <= tol
+    assert float((du / umag).max()) <= tol
+
+
+def test_con2prim_paper_grid_c3e8():
+    """The paper's 25x25 grid at c = 3e8 (SI units) through the GPU solvers."""
+    c = 3.0e8
+    G, PP = wl.c2p_grid(25, c=c)
+    g, P = G.ravel(), PP.ravel()
+    rho = 1.0 / g
+    beta = np.sqrt((1 - 1 / g) * (1 + 1 / g))
+    v = np.stack([beta * c, 0 * g, 0 * g])
+    for eos, method in ((IDEAL, NEWTON), (TM, CUBIC)):
+        cfg = wl.make_config("random3d", n_elem=(625, 1, 1), p=0, eos=eos, c2p=method, c=c)
+        st = Setup.from_config(cfg)
+        U = osrhd.prim3_to_cons(torch.tensor(rho), torch.tensor(v), torch.tensor(P), st)
+        U = U.reshape((5,) + wl.field_shape(cfg))
+        s = _solver(cfg)
+        W = s.con2prim(U.cuda()).cpu().reshape(5, -1)
+        vrec = W[1] / torch.sqrt(1 + (W[1:4] ** 2).sum(0) / c ** 2)
+        nz = beta > 0
+        err = np.abs((vrec.numpy() - beta * c)[nz] / (beta * c)[nz])
+        assert err.max() < 1e-14, (eos, err.max())
+
+
+@pytest.mark.parametrize("kind,over", [("kh_tm", {"n_elem": (10, 10, 1)}), ("random3d", {"n_elem": (4, 4, 3)}),
+                                       ("wave1d", {})])
+def test_set_state_matches_oracle(kind, over):
+    cfg = _case_cfg(kind, over)
+    st = Setup.from_config(cfg)
+    rho, v, P = wl.initial_primitives(cfg)
+    U_ref = osrhd.prim3_to_cons(*(torch.from_numpy(a) for a in (rho, v, P)), st)
+    src = torch.from_numpy(wl.pack_primitives(rho, v, P))
+    s = _solver(cfg)
+    U = s.set_state(src.cuda()).cpu()
+    err = rel_err_per_var(U, U_ref.reshape(U.shape))
+    # the map's conditioning grows like gamma^2 (gamma up to 20 in the random 3D field)
+    assert float(err.max()) <= (1e-13 if kind == "random3d" else 1e-14), err.tolist()
+
+
+def _flagged_mesh(dim, p, n_elem, seed):
+    from .test_oracle_physicality import _flagged_cells
+    st = Setup(dim=dim, p=p, n_elem=n_elem, eos=IDEAL)
+    rng = np.random.default_rng(seed)
+    nel = int(np.prod(n_elem))
+    cells = _flagged_cells(st, rng, nel)
+    U = torch.zeros((st.nvar,) + st.shape())
+    flat = U.reshape(st.nvar, nel, (p + 1) ** dim)
+    for e in range(nel):
+        if e % 3 == 2:  # leave every third element admissible
+            c = cells[e][0].clone()
+            c[0] = c[0].abs() + 1.0
+            c[1:-1] *= 0.1
+            c[-1] = c[-1].abs() + 1.0
+            flat[:, e] = c
+        else:
+            flat[:, e] = cells[e][0]
+    return st, flat.reshape(U.shape)
+
+
+@pytest.mark.parametrize("dim,p,n_elem", [(1, 2, (100, 1, 1)), (2, 2, (7, 6, 1)), (2, 3, (5, 5, 1)),
+                                          (3, 2, (4, 3, 2))])
+def test_enforce_matches_oracle(dim, p, n_elem):
+    st, U = _flagged_mesh(dim, p, n_elem, 50 + dim)
+    stats = {}
+    V_ref = ophys.enforce(U, st, stats)
+    cfg = dict(dim=dim, p=p, n_elem=n_elem, lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 0), eos=IDEAL,
+               gamma_ad=4 / 3, c=1.0, c2p=-1, precision=0, phys=True)
+    s = _solver(cfg, sync=False)
+    Ud = U.cuda().contiguous()
+    s.enforce(Ud)
+    V = Ud.cpu()
+    err = rel_err_per_var(V, V_ref)
+    assert float(err.max()) <= 1e-13, err.tolist()
+    diag = s.diagnostics()
+    assert diag["smoothed"] == stats["smoothed"] and diag["flagged"] == stats["flagged"]
+    assert diag["bad_average"] == stats.get("bad_average", 0)
+
+
+@pytest.mark.parametrize("kind,over,nsteps", [("kh_tm", {"n_elem": (12, 10, 1)}, 1),
+                                              ("kh_ideal", {"n_elem": (10, 9, 1)}, 5),
+                                              ("wave1d", {}, 10),
+                                              ("random3d", {"n_elem": (5, 4, 3)}, 1)])
+def test_ssprk3_steps_match_oracle(kind, over, nsteps):
+    cfg = _case_cfg(kind, over)
+    st, U = oracle_state(cfg)
+    stats = {}
+    U_ref = ots.run(U, cfg["dt"], nsteps, st, phys=True, stats=stats)
+    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], nsteps, st, phys=True), U)
+    s = _solver(cfg, sync=False)
+    Ud = U.cuda().contiguous()
+    if nsteps == 1:
+        s.step(Ud, cfg["dt"])
+    else:
+        s.run(Ud, cfg["dt"], nsteps)
+    err = rel_err_per_var(Ud.cpu(), U_ref)
+    print(f"err {err.tolist()} tol {tol.tolist()}")
+    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    if kind == "random3d":
+        assert s.diagnostics()["smoothed"] == stats.get("smoothed", 0)
