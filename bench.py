@@ -78,6 +78,45 @@ def _setup(kind, **over):
     return cfg, solver, U
 
 
+def adjoint_ratio(reps=2):
+    """Checkpointed adjoint (200 steps, checkpoint every 20) of J = int v_y^2 dA on the
+    128x128 p=2 ideal-gas Kelvin-Helmholtz mesh: backward time (segment recompute with
+    tapes + step adjoints + objective gradient) / forward time (200 steps + checkpoints)."""
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    from paper_2205_00095_amd.adjoint import Trajectory, VY2
+    from paper_2205_00095_amd.solver import Solver
+    cfg = wl.make_config("kh_ideal")
+    solver = Solver(cfg)
+    rho, v, P = wl.initial_primitives(cfg)
+    v = v.copy()
+    v[1] += wl.kh_perturbation(cfg)
+    U0 = solver.set_state(torch.from_numpy(wl.pack_primitives(rho, v, P)).cuda())
+    nsteps, dt, k = cfg["steps"], cfg["dt"], 20
+    stream = torch.cuda.current_stream()
+    best_f = best_b = float("inf")
+    for _ in range(reps + 1):
+        U = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        UT = Trajectory.apply(U, solver, nsteps, dt, k)
+        e1.record(stream)
+        J = VY2.apply(UT, solver)
+        torch.cuda.synchronize()
+        e1b = torch.cuda.Event(enable_timing=True)
+        e1b.record(stream)
+        J.backward()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        best_f = min(best_f, e0.elapsed_time(e1) / 1e3)
+        best_b = min(best_b, e1b.elapsed_time(e2) / 1e3)
+    dofs = wl.n_dof(cfg)
+    return {"workload": "kh_ideal: 2D 128x128 elements p=2 ideal EOS, 200 steps, checkpoint every 20",
+            "forward_s": best_f, "backward_s": best_b, "ratio": best_b / best_f,
+            "forward_dof_stage_per_s": dofs * nsteps * 3 / best_f}
+
+
 def cpu_baseline(kind="kh_tm", steps=3):
     """The oracle as it stands, on the host cores, for `steps` SSP-RK3 steps of the full mesh."""
     import torch
@@ -106,6 +145,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="kh_tm")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32, adjoint and CPU legs")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -116,6 +157,12 @@ def main(argv=None):
     from paper_2205_00095_amd import workloads as wl
 
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg, solver, U = _setup(args.workload)
     dofs = wl.n_dof(cfg)
     nvar = cfg["dim"] + 2
@@ -169,6 +216,7 @@ def main(argv=None):
             "value_fp32": d3 * n3 * 3 / t32, "value_fp64": d3 * n3 * 3 / t64,
             "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": n3}
         del s32, U32
+        extras["adjoint"] = adjoint_ratio()
         out.update(extras)
         out["cpu_baseline"] = cpu_baseline("kh_tm", args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -146,6 +146,12 @@ size_t dg_tape_size(const dg_ctx* ctx);
 int dg_ssprk3_step_tape(dg_ctx* ctx, double* U_dev, double dt, double* tape_dev);
 int dg_ssprk3_step_vjp_tape(dg_ctx* ctx, const double* tape_dev, double dt, const double* lam_next_dev,
                             double* lam_n_dev);
+/* Segment forms for checkpointed trajectories: nsteps taped steps in place on U_dev,
+ * tapes_dev holding nsteps consecutive tapes; then the nsteps step adjoints in
+ * reverse order, in place on lam_dev (lambda of the segment end on entry, of its
+ * start on exit). */
+int dg_ssprk3_run_tape(dg_ctx* ctx, double* U_dev, double dt, int nsteps, double* tapes_dev);
+int dg_ssprk3_run_vjp_tape(dg_ctx* ctx, const double* tapes_dev, double dt, int nsteps, double* lam_dev);
 
 /* J = sum over nodes of (cell volume / 2^dim) w_i v_y,i^2 (the integral of v_y^2,
  * the Kelvin-Helmholtz diagnostic of Sec. 4) written to *J_host (synchronises),

@@ -56,6 +56,8 @@ SIGNATURES = {
     "dg_tape_size": (ctypes.c_size_t, [_P]),
     "dg_ssprk3_step_tape": (_I, [_P, _P, _D, _P]),
     "dg_ssprk3_step_vjp_tape": (_I, [_P, _P, _D, _P, _P]),
+    "dg_ssprk3_run_tape": (_I, [_P, _P, _D, _I, _P]),
+    "dg_ssprk3_run_vjp_tape": (_I, [_P, _P, _D, _I, _P]),
     "dg_objective_vy2": (_I, [_P, _P, ctypes.POINTER(_D), _P]),
     "dg_set_state_vjp": (_I, [_P, _P, _P, _P]),
     "dg_get_diagnostics": (_I, [_P, ctypes.POINTER(Diag)]),

@@ -6,9 +6,9 @@ chains the pieces:
 * ``SetState``     (rho, v, P) -> U   (dg_set_state / dg_set_state_vjp)
 * ``Trajectory``   U0 -> U after nsteps SSP-RK3 steps, checkpointing U every
                    ``k`` steps in the forward pass; the backward pass recomputes
-                   each segment from its checkpoint with the taped step
-                   (dg_ssprk3_step_tape) and runs the step adjoints in reverse
-                   (dg_ssprk3_step_vjp_tape).  Memory: nsteps/k states of
+                   each segment from its checkpoint with taped steps
+                   (dg_ssprk3_run_tape) and runs the step adjoints in reverse
+                   (dg_ssprk3_run_vjp_tape).  Memory: nsteps/k states of
                    checkpoints plus k tapes of 6 states.
 * ``VY2``          U -> J = int v_y^2 dA (dg_objective_vy2 with its gradient)
 """
@@ -54,10 +54,8 @@ class Trajectory(torch.autograd.Function):
             s0 = seg * k
             n = min(k, nsteps - s0)
             U = ctx.ckpts[seg].clone()
-            for j in range(n):
-                solver.step_tape(U, dt, tapes[j])
-            for j in reversed(range(n)):
-                solver.step_vjp_tape(tapes[j], dt, lam, out=lam)
+            solver.run_tape(U, dt, n, tapes)
+            solver.run_vjp_tape(tapes, dt, n, lam)
         ctx.ckpts = None
         return lam, None, None, None, None
 

@@ -71,8 +71,11 @@ __global__ void k_sum_partials(const double* partial, int n, double* out) {
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// One forward step in place, recording (W(U^n), W(U1), W(U2), P1, P2, P3).
-int step_tape(dg_ctx* c, double* U, double dt, double* tape, const char* what) {
+// One forward step in place, recording (W(U^n), W(U1), W(U2), P1, P2, P3).  When
+// have_w0 is set, W(U^n) is already in the tape (written by the previous step);
+// next_w0, if not null, receives W(U^{n+1}) from the last stage's epilogue.
+int step_tape(dg_ctx* c, double* U, double dt, double* tape, const char* what, bool have_w0 = false,
+              double* next_w0 = nullptr) {
   const size_t S = state_doubles(c);
   double* W0 = tape;
   double* W1 = tape + S;
@@ -80,15 +83,15 @@ int step_tape(dg_ctx* c, double* U, double dt, double* tape, const char* what) {
   double* P1 = tape + 3 * S;
   double* P2 = tape + 4 * S;
   double* P3 = tape + 5 * S;
-  int r = hipcheck(c, L_con2prim(c, U, W0), what);
-  if (r) return r;
+  int r;
+  if (!have_w0 && (r = hipcheck(c, L_con2prim(c, U, W0), what))) return r;
   ElemArgs a = base_args(c);
   a.dt = dt;
   a.W = W0; a.Uk = U; a.Un = U; a.ca = 0.0; a.cb = 1.0; a.out = c->U1; a.Wout = W1; a.Pout = P1;
   if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
   a.W = W1; a.Uk = c->U1; a.ca = 0.75; a.cb = 0.25; a.out = c->U2; a.Wout = W2; a.Pout = P2;
   if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
-  a.W = W2; a.Uk = c->U2; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.out = U; a.Wout = nullptr; a.Pout = P3;
+  a.W = W2; a.Uk = c->U2; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.out = U; a.Wout = next_w0; a.Pout = P3;
   return hipcheck(c, L_element(c, MODE_STAGE, a), what);
 }
 
@@ -162,6 +165,32 @@ int dg_ssprk3_step_vjp_tape(dg_ctx* c, const double* tape, double dt, const doub
   if (r) return r;
   if ((r = step_vjp_tape(c, tape, dt, lam_next, lam_n, "dg_ssprk3_step_vjp_tape"))) return r;
   return finish(c, "dg_ssprk3_step_vjp_tape");
+}
+
+int dg_ssprk3_run_tape(dg_ctx* c, double* U, double dt, int nsteps, double* tapes) {
+  if (!c) return DG_EINVAL;
+  if (!U || !tapes) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: null pointer");
+  if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: nsteps < 0");
+  const size_t T = 6 * state_doubles(c);
+  for (int s = 0; s < nsteps; ++s) {
+    double* next_w0 = (s + 1 < nsteps) ? tapes + (size_t)(s + 1) * T : nullptr;
+    int r = step_tape(c, U, dt, tapes + (size_t)s * T, "dg_ssprk3_run_tape", s > 0, next_w0);
+    if (r) return r;
+  }
+  return finish(c, "dg_ssprk3_run_tape");
+}
+
+int dg_ssprk3_run_vjp_tape(dg_ctx* c, const double* tapes, double dt, int nsteps, double* lam) {
+  if (!c) return DG_EINVAL;
+  if (!tapes || !lam) return fail(c, DG_EINVAL, "dg_ssprk3_run_vjp_tape: null pointer");
+  if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_vjp_tape: nsteps < 0");
+  int r = ensure_adj(c);
+  if (r) return r;
+  const size_t T = 6 * state_doubles(c);
+  for (int s = nsteps - 1; s >= 0; --s) {
+    if ((r = step_vjp_tape(c, tapes + (size_t)s * T, dt, lam, lam, "dg_ssprk3_run_vjp_tape"))) return r;
+  }
+  return finish(c, "dg_ssprk3_run_vjp_tape");
 }
 
 int dg_ssprk3_step_vjp(dg_ctx* c, const double* Un, double dt, const double* lam_next, double* lam_n) {

@@ -313,8 +313,9 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_rhs_vjp(VjpArgs a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) Wn[v] = src[v * ntot];
       }
-      if (side) hll_flux_rev<EOS, DIM>(Wo, Wn, d, q, lamFh, lamWo, lamWn);
-      else hll_flux_rev<EOS, DIM>(Wn, Wo, d, q, lamFh, lamWn, lamWo);
+      // only this element's side is needed: the neighbour reverses its own side
+      if (side) hll_flux_rev<EOS, DIM>(Wo, Wn, d, q, lamFh, lamWo, lamWn, true, false);
+      else hll_flux_rev<EOS, DIM>(Wn, Wo, d, q, lamFh, lamWn, lamWo, false, true);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) sLW[v * FPB + fp] = lamWo[v];

@@ -71,11 +71,26 @@ struct ElemArgs {
   Counters* cnt;
 };
 
+// Wave-aggregated event counting: one atomic per wave and counter (the counters are
+// hit by many lanes at once on stress data; per-lane atomics on one address serialise).
+__device__ __forceinline__ void count_wave(unsigned long long* ctr, bool flag) {
+  const unsigned long long m = __ballot(flag);
+  if (m == 0ull) return;
+  const int leader = __ffsll((long long)m) - 1;
+  if ((int)(threadIdx.x & 63) == leader) atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
+// Recovery status: counts failures / non-convergence and records an element index
+// with a failure (the first failing lane of each wave offers its element to an
+// atomic minimum).
 __device__ __forceinline__ void count_c2p(Counters* cnt, int status, long long elem) {
-  if (status == C2P_OK) return;
-  if (status == C2P_NOCONV) atomicAdd(&cnt->c2p_noconv, 1ull);
-  else atomicAdd(&cnt->c2p_fail, 1ull);
-  atomicMin(&cnt->first_bad, (unsigned long long)elem);
+  const bool fail = status != C2P_OK && status != C2P_NOCONV;
+  const bool noconv = status == C2P_NOCONV;
+  count_wave(&cnt->c2p_fail, fail);
+  count_wave(&cnt->c2p_noconv, noconv);
+  const unsigned long long m = __ballot(fail || noconv);
+  if (m != 0ull && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1)
+    atomicMin(&cnt->first_bad, (unsigned long long)elem);
 }
 
 // index of the node along direction d
@@ -161,10 +176,10 @@ __global__ __launch_bounds__(256) void k_prim3_to_cons(const double* __restrict_
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = s.U[v];
   } else {
-    atomicAdd(&cnt->bad_input, 1ull);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = 0.0;
   }
+  count_wave(&cnt->bad_input, !ok);
 #pragma unroll
   for (int v = 0; v < NV; ++v) U[v * ntot + n] = out[v];
 }
@@ -215,12 +230,12 @@ __device__ __forceinline__ double node_factor(const double* Ui, const double* Ub
 // Apply the operator to the elements of one workgroup.  Every thread holds one
 // node's U in registers (act = it belongs to a real element); sbuf must hold
 // NV * NT doubles and sflag NT ints.  Must be reached by all threads of the block.
-template <int DIM, int P>
-__device__ __forceinline__ void physicality_block(double* Un, bool act, int tid, int el, int node, long long e,
+template <int DIM, int P, int NTB>
+__device__ __forceinline__ void physicality_block_t(double* Un, bool act, int tid, int el, int node,
                                                   const Tables& t, const PhysParams& q, Counters* cnt,
                                                   double* sbuf, int* sflag) {
   using G = Geo<DIM, P>;
-  constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, N1 = G::N1;
+  constexpr int NV = G::NV, NPE = G::NPE, NT = NTB, N1 = G::N1;
   const bool bad = act && !admissible<DIM>(Un, q);
   if (!__syncthreads_or(bad)) return;
   double wn = t.w[node_coord<N1>(node, 0)];
@@ -244,11 +259,11 @@ __device__ __forceinline__ void physicality_block(double* Un, bool act, int tid,
     }
     avg_ok = admissible<DIM>(Ub, q);
     if (avg_ok) s = node_factor<DIM>(Un, Ub, q);
-    if (node == 0) {
-      atomicAdd(&cnt->flagged, 1ull);
-      atomicAdd(avg_ok ? &cnt->smoothed : &cnt->bad_average, 1ull);
-    }
   }
+  const bool lead = act && eflag && node == 0;
+  count_wave(&cnt->flagged, lead);
+  count_wave(&cnt->smoothed, lead && avg_ok);
+  count_wave(&cnt->bad_average, lead && !avg_ok);
   __syncthreads();
   sbuf[tid] = s;
   __syncthreads();
@@ -276,7 +291,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
   double u[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = act ? U[v * m.ntot + g] : 1.0;
-  physicality_block<DIM, P>(u, act, tid, el, node, e, t, q, cnt, sbuf, sflag);
+  physicality_block_t<DIM, P, NT>(u, act, tid, el, node, t, q, cnt, sbuf, sflag);
   if (act) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) U[v * m.ntot + g] = u[v];
@@ -287,15 +302,66 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
 enum { MODE_RHS = 0, MODE_STAGE = 1 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1 };
 
-template <int DIM, int P, int EOS, int PREC, int MODE>
-__global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_element(ElemArgs a) {
+// Tile of elements handled by one workgroup of k_element: TX x TY x TZ elements,
+// one node per lane.  Faces inside the tile are evaluated once and shared by the
+// two elements through LDS; only the tile's boundary faces are evaluated again by
+// the neighbouring tile.
+template <int DIM, int P>
+struct TileGeo {
   using G = Geo<DIM, P>;
-  constexpr int N1 = G::N1, NPE = G::NPE, NV = G::NV, NT = G::NT, EPB = G::EPB;
-  constexpr int NFP = G::NFP, NF = G::NF, FPB = G::FPB;
+  static constexpr int N1 = G::N1, NPE = G::NPE, NV = G::NV, NFP = G::NFP;
+  static constexpr int TX = DIM == 1 ? G::EPB
+                          : DIM == 2 ? (P == 0 ? 16 : P == 1 ? 8 : P == 2 ? 7 : 4)
+                                     : (P == 0 ? 8 : P == 1 ? 4 : P == 2 ? 3 : 2);
+  static constexpr int TY = DIM == 1 ? 1 : DIM == 2 ? (P == 0 ? 16 : P == 1 ? 8 : 4)
+                                                    : (P == 0 ? 8 : P == 1 ? 4 : P == 2 ? 3 : 2);
+  static constexpr int TZ = DIM < 3 ? 1 : (P == 0 ? 4 : P == 1 ? 2 : 1);
+  static constexpr int EPB = TX * TY * TZ;
+  static constexpr int NT = EPB * NPE;
+  static constexpr int NFX = (TX + 1) * TY * TZ;
+  static constexpr int NFY = DIM > 1 ? TX * (TY + 1) * TZ : 0;
+  static constexpr int NFZ = DIM > 2 ? TX * TY * (TZ + 1) : 0;
+  static constexpr int FOFF1 = NFX * NFP;
+  static constexpr int FOFF2 = FOFF1 + NFY * NFP;
+  static constexpr int FPB = FOFF2 + NFZ * NFP;  // face points per tile
+  static_assert(NT <= 256, "tile larger than a workgroup");
+};
+
+// index of the face point (direction d, face coordinate f along d, the other two local
+// element coordinates, point pt) in the tile's face-point list
+template <int DIM, int P>
+__device__ __forceinline__ int tile_face_index(int d, int f, const int* l, int pt) {
+  using T = TileGeo<DIM, P>;
+  int fi;
+  if (d == 0) fi = (l[2] * T::TY + l[1]) * (T::TX + 1) + f;
+  else if (d == 1) fi = (l[2] * (T::TY + 1) + f) * T::TX + l[0];
+  else fi = (f * T::TY + l[1]) * T::TX + l[0];
+  const int off = d == 0 ? 0 : (d == 1 ? T::FOFF1 : T::FOFF2);
+  return off + fi * T::NFP + pt;
+}
+
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs
+// (hardware block b runs on XCD b % 8), so hardware block b is mapped to logical
+// tile start(x) + b / 8, where XCD x owns the contiguous range of nb/8 (+1 for the
+// first nb % 8 XCDs) tiles starting at start(x).  Neighbouring tiles, which read
+// each other's halo primitives, then share one XCD's L2.  A bijection for any nb.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * q + min(x, r) + k;
+}
+
+#ifndef DG_ELEM_MIN_BLOCKS
+#define DG_ELEM_MIN_BLOCKS 1
+#endif
+template <int DIM, int P, int EOS, int PREC, int MODE>
+__global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_element(ElemArgs a) {
+  using T = TileGeo<DIM, P>;
+  constexpr int N1 = T::N1, NPE = T::NPE, NV = T::NV, NT = T::NT, EPB = T::EPB;
+  constexpr int NFP = T::NFP, FPB = T::FPB, TX = T::TX, TY = T::TY, TZ = T::TZ;
   __shared__ double sW[NV * NT];
   __shared__ double sF[NV * NT];
   __shared__ double sFh[NV * FPB];
-  // FP32 form: per-line FP64 reference flux (the flux at the line's first node)
   __shared__ double sFref[(PREC == PREC_FP32) ? DIM * NV * EPB * NFP : 1];
   __shared__ int sflag[(MODE == MODE_STAGE) ? NT : 1];
 
@@ -305,10 +371,15 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_element(ElemArgs a) {
   const long long ntot = m.ntot;
   const int tid = threadIdx.x;
   const int el = tid / NPE, node = tid % NPE;
-  const int e0 = blockIdx.x * EPB;
-  const int e = e0 + el;
-  const bool act = e < m.nelem;
-  const long long g = (long long)e * NPE + node;
+  // tile origin
+  const int ntx = (m.nex + TX - 1) / TX, nty = (m.ney + TY - 1) / TY, ntz = (m.nez + TZ - 1) / TZ;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
+  const int o[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * TZ};
+  const int nn[3] = {m.nex, m.ney, m.nez};
+  const int lc[3] = {el % TX, (el / TX) % TY, el / (TX * TY)};
+  const bool act = (o[0] + lc[0] < m.nex) && (o[1] + lc[1] < m.ney) && (o[2] + lc[2] < m.nez);
+  const long long e = act ? ((long long)(o[2] + lc[2]) * m.ney + (o[1] + lc[1])) * m.nex + (o[0] + lc[0]) : 0;
+  const long long g = e * NPE + node;
 
   double W[NV];
 #pragma unroll
@@ -360,87 +431,152 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_element(ElemArgs a) {
   }
   __syncthreads();
 
-  // ---- faces: primitive traces, exterior state, HLL flux per face point
+  // ---- faces of the tile: primitive traces (FP64), exterior states, HLL flux per face point
+  unsigned nfb = 0;  // trace fallbacks seen by this lane
   for (int fp = tid; fp < FPB; fp += NT) {
-    const int fel = fp / (NF * NFP);
-    const int rem = fp - fel * NF * NFP;
-    const int f = rem / NFP;
-    const int pt = rem - f * NFP;
-    const int fe = e0 + fel;
-    if (fe >= m.nelem) continue;
-    const int d = f >> 1;
-    const int side = f & 1;  // 1: the + face of the element
-    const double* lo = side ? t.lp : t.lm;
-    const double* ln = side ? t.lm : t.lp;
-    const float* lof = side ? t.lp_f : t.lm_f;
-    const float* lnf = side ? t.lm_f : t.lp_f;
-    double Wo[NV], Wn[NV];
-    const int ob = fel * NPE;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if constexpr (PREC == PREC_FP64) {
-        double acc = 0.0;
-#pragma unroll
-        for (int aa = 0; aa < N1; ++aa) acc += lo[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
-        Wo[v] = acc;
-      } else {
-        const double ref = sW[v * NT + ob + line_node<DIM, N1>(d, pt, 0)];
-        float acc = 0.0f;
-#pragma unroll
-        for (int aa = 0; aa < N1; ++aa) acc += lof[aa] * (float)(sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)] - ref);
-        Wo[v] = ref + (double)acc;
-      }
-    }
-    if (!(Wo[0] > 0.0) || !(Wo[NV - 1] > 0.0)) {
-      const int nb = ob + line_node<DIM, N1>(d, pt, side ? P : 0);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Wo[v] = sW[v * NT + nb];
-      atomicAdd(&a.cnt->trace_fallback, 1ull);
-    }
-    const int ne = neighbour(m, fe, d, side ? 1 : -1);
-    if (ne < 0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Wn[v] = Wo[v];
+    int d, fi;
+    if (fp < T::FOFF1) { d = 0; fi = fp; }
+    else if (DIM > 1 && fp < T::FOFF2) { d = 1; fi = fp - T::FOFF1; }
+    else { d = 2; fi = fp - T::FOFF2; }
+    const int face = fi / NFP;
+    const int pt = fi - face * NFP;
+    int l[3], f;
+    if (d == 0) {
+      f = face % (TX + 1); l[1] = (face / (TX + 1)) % TY; l[2] = face / ((TX + 1) * TY); l[0] = 0;
+    } else if (d == 1) {
+      l[0] = face % TX; f = (face / TX) % (TY + 1); l[2] = face / (TX * (TY + 1)); l[1] = 0;
     } else {
-      const long long nbase = (long long)ne * NPE;
+      l[0] = face % TX; l[1] = (face / TX) % TY; f = face / (TX * TY); l[2] = 0;
+    }
+    // the face lies between local elements f-1 and f along d
+    bool other_ok = true;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double* src = a.W + v * ntot + nbase;
-        if constexpr (PREC == PREC_FP64) {
+    for (int k = 0; k < 3; ++k)
+      if (k != d && o[k] + l[k] >= nn[k]) other_ok = false;
+    const int gl = o[d] + f - 1, gr = o[d] + f;
+    const bool left_local = other_ok && f >= 1 && gl < nn[d];
+    const bool right_local = other_ok && f <= (d == 0 ? TX : d == 1 ? TY : TZ) - 1 && gr < nn[d];
+    if (!left_local && !right_local) continue;
+    double WL[NV], WR[NV];
+    bool have_L = true, have_R = true;
+    // left state: + trace of the left element
+    {
+      int lcl[3] = {l[0], l[1], l[2]};
+      lcl[d] = f - 1;
+      if (left_local) {
+        const int ob = ((lcl[2] * TY + lcl[1]) * TX + lcl[0]) * NPE;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
           double acc = 0.0;
 #pragma unroll
-          for (int aa = 0; aa < N1; ++aa) acc += ln[aa] * src[line_node<DIM, N1>(d, pt, aa)];
-          Wn[v] = acc;
-        } else {
-          const double ref = src[line_node<DIM, N1>(d, pt, 0)];
-          float acc = 0.0f;
+          for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
+          WL[v] = acc;
+        }
+        if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
+          const int nb = ob + line_node<DIM, N1>(d, pt, P);
 #pragma unroll
-          for (int aa = 0; aa < N1; ++aa) acc += lnf[aa] * (float)(src[line_node<DIM, N1>(d, pt, aa)] - ref);
-          Wn[v] = ref + (double)acc;
+          for (int v = 0; v < NV; ++v) WL[v] = sW[v * NT + nb];
+          nfb++;
+        }
+      } else {
+        int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
+        gc[d] = gl;
+        if (gc[d] < 0) {
+          if (m.periodic[d]) gc[d] += nn[d];
+          else have_L = false;
+        }
+        if (have_L) {
+          const long long nbase = (((long long)gc[2] * m.ney + gc[1]) * m.nex + gc[0]) * NPE;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const double* src = a.W + v * ntot + nbase;
+            double acc = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * src[line_node<DIM, N1>(d, pt, aa)];
+            WL[v] = acc;
+          }
+          if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
+            const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, P);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) WL[v] = src[v * ntot];
+            nfb++;
+          }
         }
       }
-      if (!(Wn[0] > 0.0) || !(Wn[NV - 1] > 0.0)) {
-        const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, side ? 0 : P);
+    }
+    // right state: - trace of the right element
+    {
+      int lcl[3] = {l[0], l[1], l[2]};
+      lcl[d] = f;
+      if (right_local) {
+        const int ob = ((lcl[2] * TY + lcl[1]) * TX + lcl[0]) * NPE;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Wn[v] = src[v * ntot];
-        atomicAdd(&a.cnt->trace_fallback, 1ull);
+        for (int v = 0; v < NV; ++v) {
+          double acc = 0.0;
+#pragma unroll
+          for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
+          WR[v] = acc;
+        }
+        if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
+          const int nb = ob + line_node<DIM, N1>(d, pt, 0);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) WR[v] = sW[v * NT + nb];
+          nfb++;
+        }
+      } else {
+        int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
+        gc[d] = gr;
+        if (gc[d] >= nn[d]) {
+          if (m.periodic[d]) gc[d] -= nn[d];
+          else have_R = false;
+        }
+        if (have_R) {
+          const long long nbase = (((long long)gc[2] * m.ney + gc[1]) * m.nex + gc[0]) * NPE;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const double* src = a.W + v * ntot + nbase;
+            double acc = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * src[line_node<DIM, N1>(d, pt, aa)];
+            WR[v] = acc;
+          }
+          if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
+            const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, 0);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) WR[v] = src[v * ntot];
+            nfb++;
+          }
+        }
       }
     }
+    // outflow boundary: the exterior state equals the interior trace
+    if (!have_L) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) WL[v] = WR[v];
+    }
+    if (!have_R) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) WR[v] = WL[v];
+    }
     double Fh[NV];
-    if (side) hll_flux<EOS, DIM>(Wo, Wn, d, q, Fh);
-    else hll_flux<EOS, DIM>(Wn, Wo, d, q, Fh);
+    hll_flux<EOS, DIM>(WL, WR, d, q, Fh);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sFh[v * FPB + fp] = Fh[v];
   }
-  __syncthreads();
+  if (__syncthreads_or(nfb != 0)) {  // block-uniform; all lanes active here
+    unsigned long long w = nfb;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
+    if ((tid & 63) == 0 && w != 0ull) atomicAdd(&a.cnt->trace_fallback, w);
+  }
 
   // ---- lift: S_i = -sum_d (2/dx_d)(1/w_{i_d}) [l_{i_d}(+1) Fhat^+ - l_{i_d}(-1) Fhat^-]
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const int id = node_coord<N1>(node, d);
     const int pt = face_pt<DIM, N1>(node, d);
-    const int ip = (el * NF + 2 * d + 1) * NFP + pt;
-    const int im = (el * NF + 2 * d) * NFP + pt;
+    const int im = tile_face_index<DIM, P>(d, lc[d], lc, pt);
+    const int ip = tile_face_index<DIM, P>(d, lc[d] + 1, lc, pt);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if constexpr (PREC == PREC_FP64) {
@@ -478,7 +614,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_element(ElemArgs a) {
     }
     if (a.phys) {
       __syncthreads();
-      physicality_block<DIM, P>(Un, act, tid, el, node, e, t, q, a.cnt, sF, sflag);
+      physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, a.cnt, sF, sflag);
     }
     if (act) {
 #pragma unroll

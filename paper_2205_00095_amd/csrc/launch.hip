@@ -13,9 +13,10 @@ namespace {
 
 template <int DIM, int P, int EOS, int PREC, int MODE>
 hipError_t run_element(const ElemArgs& a, hipStream_t s) {
-  using G = Geo<DIM, P>;
-  const int nb = (a.m.nelem + G::EPB - 1) / G::EPB;
-  hipLaunchKernelGGL((k_element<DIM, P, EOS, PREC, MODE>), dim3(nb), dim3(G::NT), 0, s, a);
+  using T = TileGeo<DIM, P>;
+  const int nb = ((a.m.nex + T::TX - 1) / T::TX) * ((a.m.ney + T::TY - 1) / T::TY) *
+                 ((a.m.nez + T::TZ - 1) / T::TZ);
+  hipLaunchKernelGGL((k_element<DIM, P, EOS, PREC, MODE>), dim3(nb), dim3(T::NT), 0, s, a);
   return hipGetLastError();
 }
 

@@ -66,6 +66,7 @@ struct StateEval {
   double g2, ig;  // gamma^2, 1/gamma
   double P;
   double th, he;  // Theta, h - c^2
+  double sq;      // Taub-Matthews: sqrt(Theta^2 + 4/9 c^4)
 };
 
 template <int EOS, int DIM>
@@ -76,9 +77,17 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
 #pragma unroll
   for (int j = 0; j < DIM; ++j) usq += W[1 + j] * W[1 + j];
   const double g2 = 1.0 + usq * q.inv_c2;
-  const double g = sqrt(g2);
+  const double ig = 1.0 / sqrt(g2);
+  const double g = g2 * ig;
   const double th = P / rho;
-  const double he = h_excess<EOS>(th, q);
+  double he;
+  if constexpr (EOS == EOS_IDEAL) {
+    he = q.alpha * th;
+    s.sq = 0.0;
+  } else {
+    s.sq = sqrt(th * th + (4.0 / 9.0) * q.c4);
+    he = 2.5 * th + 1.5 * th * th / (s.sq + (2.0 / 3.0) * q.c2);
+  }
   const double D = g * rho;
   const double gH = g * rho * (q.c2 + he) * q.inv_c2;  // gamma rho h / c^2
   s.U[0] = D;
@@ -87,7 +96,7 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
   // tau = gamma^2 rho h - P - D c^2 = D |u|^2/(gamma+1) + gamma^2 rho (h - c^2) - P
   s.U[DIM + 1] = D * usq / (g + 1.0) + g2 * rho * he - P;
   s.g2 = g2;
-  s.ig = 1.0 / g;
+  s.ig = ig;
   s.P = P;
   s.th = th;
   s.he = he;
@@ -111,14 +120,22 @@ __host__ __device__ __forceinline__ void flux_dir(const double* W, const StateEv
 // sigma = c_s^2 / (gamma^2 (c^2 - c_s^2)).
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void wavespeeds(const double* W, const StateEval<EOS, DIM>& s, int d,
-                                           const PhysParams& q, double& lm, double& lp) {
-  const double cs2 = sound2<EOS>(s.th, s.he, q);
+                                                   const PhysParams& q, double& lm, double& lp) {
+  double cs2;
+  if constexpr (EOS == EOS_IDEAL) {
+    cs2 = q.c2 * q.gam * s.th / (q.c2 + s.he);
+  } else {
+    const double th = s.th;
+    cs2 = q.c2 * (3.0 * th * th + 5.0 * th * s.sq) / (12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s.sq);
+  }
   const double vd = W[1 + d] * s.ig;
-  const double sigma = cs2 / (s.g2 * (q.c2 - cs2));
-  const double root = sqrt(sigma * (q.c2 - vd * vd + q.c2 * sigma));
-  const double inv = 1.0 / (1.0 + sigma);
-  lm = (vd - root) * inv;
-  lp = (vd + root) * inv;
+  // with den = gamma^2 (c^2 - c_s^2), sigma = c_s^2/den and
+  // lambda_pm = (vd den pm sqrt(c_s^2 (den (c^2 - vd^2) + c^2 c_s^2))) / (den + c_s^2)
+  const double den = s.g2 * (q.c2 - cs2);
+  const double root = sqrt(cs2 * (den * (q.c2 - vd * vd) + q.c2 * cs2));
+  const double inv = 1.0 / (den + cs2);
+  lm = (vd * den - root) * inv;
+  lp = (vd * den + root) * inv;
 }
 
 // HLL numerical flux along d between left and right primitive states
@@ -171,11 +188,11 @@ __host__ __device__ __forceinline__ double cube_root(double x) { return cbrt(x);
 __host__ __device__ __forceinline__ void tm_cubic_coeffs(double xi, double eta, double& c1, double& c2, double& c3) {
   const double x2 = xi * xi, e2 = eta * eta;
   const double dm = (eta - xi) * (eta + xi);
-  const double den = dm * dm;
+  const double i16 = 1.0 / (16.0 * dm * dm);
   const double k = 4.0 * (e2 + x2) - (x2 + 1.0);
-  c1 = ((e2 + x2) * k - 14.0 * x2 * e2) / (2.0 * den);
-  c2 = (k * k - 57.0 * x2 * e2) / (16.0 * den);
-  c3 = -9.0 * x2 * e2 / (16.0 * den);
+  c1 = 8.0 * ((e2 + x2) * k - 14.0 * x2 * e2) * i16;
+  c2 = (k * k - 57.0 * x2 * e2) * i16;
+  c3 = -9.0 * x2 * e2 * i16;
 }
 
 // Brent's bracketed root finder (inverse quadratic interpolation / secant with
@@ -337,16 +354,16 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
         }
       } else {
         // analytic (trigonometric / Cardano), then one Newton step on the cubic
-        const double Q = (3.0 * c2 - c1 * c1) / 9.0;
-        const double R = (9.0 * c1 * c2 - 27.0 * c3 - 2.0 * c1 * c1 * c1) / 54.0;
+        const double Q = (3.0 * c2 - c1 * c1) * (1.0 / 9.0);
+        const double R = (9.0 * c1 * c2 - 27.0 * c3 - 2.0 * c1 * c1 * c1) * (1.0 / 54.0);
         const double dd = Q * Q * Q + R * R;
         if (dd < 0.0) {
-          double arg = R / sqrt(-Q * Q * Q);
+          double arg = R * rsqrt(-Q * Q * Q);
           arg = fmin(1.0, fmax(-1.0, arg));
-          Wc = 2.0 * sqrt(-Q) * cos(acos(arg) / 3.0) - c1 / 3.0;
+          Wc = 2.0 * sqrt(-Q) * cos(acos(arg) * (1.0 / 3.0)) - c1 * (1.0 / 3.0);
         } else {
           const double sd = sqrt(dd);
-          Wc = -c1 / 3.0 + cube_root(R + sd) + cube_root(R - sd);
+          Wc = -c1 * (1.0 / 3.0) + cube_root(R + sd) + cube_root(R - sd);
         }
         const double f = ((Wc + c1) * Wc + c2) * Wc + c3;
         const double fp = (3.0 * Wc + 2.0 * c1) * Wc + c2;
@@ -355,7 +372,7 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
       Wc = fmax(Wc, 0.0);
       const double gam = sqrt(1.0 + Wc);
       const double beta = sqrt(Wc / (Wc + 1.0));
-      gb = sqrt(Wc);
+      gb = sqrt(Wc);  // gamma beta
       rho = D / gam;
       // P = (X^2 - (rho c^2)^2)/(3X), X = E - M.v, via X_ = X - rho c^2
       const double Xm = tau - Smag * beta * q.c + D * q.c2 * Wc / (gam * (gam + 1.0));

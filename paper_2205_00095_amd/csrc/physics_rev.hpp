@@ -157,7 +157,8 @@ __host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, i
 // Adjoint of hll_flux(WL, WR, d): accumulates into lam_WL and lam_WR.
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void hll_flux_rev(const double* WL, const double* WR, int d, const PhysParams& q,
-                                             const double* lam_Fh, double* lam_WL, double* lam_WR) {
+                                             const double* lam_Fh, double* lam_WL, double* lam_WR,
+                                             bool need_L = true, bool need_R = true) {
   constexpr int NV = DIM + 2;
   StateEval<EOS, DIM> sL, sR;
   eval_state<EOS, DIM>(WL, q, sL);
@@ -199,8 +200,8 @@ __host__ __device__ __forceinline__ void hll_flux_rev(const double* WL, const do
     if (lmL <= lmR) lam_lmL = lam_aL; else lam_lmR = lam_aL;
     if (lpL >= lpR) lam_lpL = lam_aR; else lam_lpR = lam_aR;
   }
-  state_flux_speed_rev<EOS, DIM>(WL, d, q, lam_UL, lam_FL, lam_lmL, lam_lpL, speeds, lam_WL);
-  state_flux_speed_rev<EOS, DIM>(WR, d, q, lam_UR, lam_FR, lam_lmR, lam_lpR, speeds, lam_WR);
+  if (need_L) state_flux_speed_rev<EOS, DIM>(WL, d, q, lam_UL, lam_FL, lam_lmL, lam_lpL, speeds, lam_WL);
+  if (need_R) state_flux_speed_rev<EOS, DIM>(WR, d, q, lam_UR, lam_FR, lam_lmR, lam_lpR, speeds, lam_WR);
 }
 
 // J[r][c] = dU_r / dW_c at the primitive state W (Eq. primitive_to_conserved).

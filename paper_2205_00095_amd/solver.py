@@ -159,6 +159,25 @@ class Solver:
                     "dg_ssprk3_step_vjp_tape")
         return lam
 
+    def _tapes_ptr(self, tapes: torch.Tensor, nsteps: int) -> ctypes.c_void_p:
+        if tapes.dtype != torch.float64 or not tapes.is_cuda or not tapes.is_contiguous():
+            raise ValueError("tapes must be a contiguous float64 GPU tensor")
+        if tapes.numel() < nsteps * self.tape_numel:
+            raise ValueError(f"tapes holds {tapes.numel()} elements, need {nsteps * self.tape_numel}")
+        return ctypes.c_void_p(tapes.data_ptr())
+
+    def run_tape(self, U: torch.Tensor, dt: float, nsteps: int, tapes: torch.Tensor):
+        self._sync_stream()
+        self._check(self.lib.dg_ssprk3_run_tape(self.ctx, self._ptr(U, "U"), float(dt), int(nsteps),
+                                                self._tapes_ptr(tapes, nsteps)), "dg_ssprk3_run_tape")
+        return U
+
+    def run_vjp_tape(self, tapes: torch.Tensor, dt: float, nsteps: int, lam: torch.Tensor):
+        self._sync_stream()
+        self._check(self.lib.dg_ssprk3_run_vjp_tape(self.ctx, self._tapes_ptr(tapes, nsteps), float(dt),
+                                                    int(nsteps), self._ptr(lam, "lam")), "dg_ssprk3_run_vjp_tape")
+        return lam
+
     def objective_vy2(self, U: torch.Tensor, grad: bool = False):
         J = ctypes.c_double()
         g = self.empty() if grad else None

@@ -32,10 +32,11 @@ def perturbed(U, rel=1e-15, seed=0):
 
 def parity_tol(fn, U, floor=1e-12):
     """Acceptance bar for GPU-vs-oracle parity of X = fn(U): 1e-12 normwise relative per
-    component, or the oracle's own response to a ~5-ulp relative perturbation of its input
-    when the problem's FP64 conditioning makes that larger (cancellation-dominated RHS,
-    chaotic stress data).  Returns (tol, sensitivity) per component."""
+    component, or 4x the oracle's own response to ~5-ulp relative perturbations of its
+    input (max over two seeds) when the problem's FP64 conditioning makes that larger
+    (cancellation-dominated RHS, chaotic stress data).  Returns (tol, sensitivity)."""
     X0 = fn(U)
-    X1 = fn(perturbed(U))
-    sens = rel_err_per_var(X1, X0)
-    return torch.clamp(sens, min=floor), sens
+    sens = torch.maximum(rel_err_per_var(fn(perturbed(U, seed=0)), X0),
+                         rel_err_per_var(fn(perturbed(U, seed=1)), X0))
+    # one or two random perturbations under-sample the worst case: allow 4x
+    return torch.clamp(4.0 * sens, min=floor), sens

@@ -5,7 +5,7 @@ Bars: vector-Jacobian products agree with the oracle's reverse mode to 1e-9
 normwise relative per component on smooth data (the benchmark spec asks 1e-6; the
 implicit-function-theorem and hand-reversed HLL reach rounding level); the
 trajectory gradient of J = int v_y^2 dA agrees with central differences to
-1e-6 relative per direction."""
+1e-6 per direction, relative to max(|<g, v>|, 1e-3 |g|) (best of a step sweep)."""
 import numpy as np
 import pytest
 import torch
@@ -200,14 +200,18 @@ def test_trajectory_gradient_fd_kh_adjoint_workload():
     g = src.grad[2]
     dirs = torch.from_numpy(wl.random_directions(cfg, 16)).cuda()
     worst = 0.0
+    gnorm = float(g.norm())
     for k in range(16):
         ad = float((g * dirs[k]).sum())
+        # a direction almost orthogonal to the gradient is measured against 1e-3 |g|
+        scale = max(abs(ad), 1e-3 * gnorm)
         errs = []
-        for hr in (1e-5, 1e-6, 1e-7):
+        for hr in (1e-3, 1e-4, 1e-5, 1e-6):
             h = hr * float(d0.norm())
             fd = (J_of(d0 + h * dirs[k]) - J_of(d0 - h * dirs[k])) / (2 * h)
-            errs.append(abs(fd - ad) / abs(ad))
-        print(f"direction {k}: FD relative errors (h = 1e-5, 1e-6, 1e-7 |delta|) {errs}", flush=True)
+            errs.append(abs(fd - ad) / scale)
+        print(f"direction {k}: <g,v>/|g| = {ad / float(g.norm()):.3e}; FD relative errors "
+              f"(h = 1e-3 .. 1e-6 |delta|) {errs}", flush=True)
         worst = max(worst, min(errs))
     print(f"KH adjoint workload: max over 16 directions of the best-step FD error {worst:.3e}", flush=True)
     assert worst <= 1e-6

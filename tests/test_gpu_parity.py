@@ -2,9 +2,9 @@
 
 Inputs are the seeded workloads converted by the oracle's own prim->cons, so
 both sides see the same U.  Acceptance per conserved component k:
-||X_gpu,k - X_oracle,k||_inf / ||X_oracle,k||_inf <= max(1e-12, s_k), where s_k
+||X_gpu,k - X_oracle,k||_inf / ||X_oracle,k||_inf <= max(1e-12, 4 s_k), where s_k
 is the oracle's own normwise change when its input is perturbed by ~5 ulps
-(tests/_util.parity_tol).  s_k < 1e-12 for the Kelvin-Helmholtz and 3D RHS
+(max over two seeds, tests/_util.parity_tol).  s_k < 1e-12 for the Kelvin-Helmholtz and 3D RHS
 cases, so the bar there is the plain 1e-12; it exceeds 1e-12 only where FP64
 conditioning forbids 1e-12 for any two roundings (the uniform-pressure contact
 wave, whose flux-divergence terms are ~1e3 x its RHS, and a full step on the
