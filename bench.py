@@ -29,11 +29,33 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue model of MI355X: 256 CUs x 4 SIMDs at 2.4 GHz, one wave64 VALU
+# instruction per SIMD every 4 cycles (16 lanes) -- the FP64 vector peak of
+# 78.6 TFLOP/s is this rate with every instruction an FMA
+SIMDS, CLOCK_HZ, VALU_CYCLES_PER_WAVE_INST = 1024, 2.4e9, 4.0
 
 
 def _stage_bytes_per_dof(nvar: int) -> float:
     """Mean algorithmic bytes per DOF over the three stages of one step."""
     return nvar * 8.0 * (2.0 + 2.0 / 3.0)
+
+
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def _measured_traffic(workload: str):
+    """HBM bytes per stage launch from the committed counter summary of this workload
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for a plain
+    copy), or None when there is none or the kernel sources changed since it was taken."""
+    from paper_2205_00095_amd import build
+    path = os.path.join(PROFILE_DIR, f"k_element_stage_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != build.source_digest():
+        return None
+    return rec
 
 
 def _time_run(solver, U, dt, steps, warmup):
@@ -117,6 +139,60 @@ def adjoint_ratio(reps=2):
             "forward_dof_stage_per_s": dofs * nsteps * 3 / best_f}
 
 
+def con2prim_study(runs=100):
+    """The paper's recovery study (Sec. 3.3) on one MI355X: for each of the 25x25 (gamma, P)
+    states (gamma log-spaced in [1, 100], P log-spaced in [1e5, 1e10] Pa, D = 1, c = 3e8),
+    a 10x10x10 mesh of p=2 elements (27 points per cell) filled with that state is
+    recovered `runs` times by each of the four solvers; reported: recoveries/s per state
+    (median, min, max over the grid) and the relative velocity error."""
+    import numpy as np
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    from paper_2205_00095_amd.solver import Solver
+    c = 3.0e8
+    G, PP = wl.c2p_grid(25, c=c)
+    out = {}
+    stream = torch.cuda.current_stream()
+    for eos, method, name in ((wl.EOS_IDEAL, wl.C2P_NEWTON, "ideal_newton"), (wl.EOS_IDEAL, wl.C2P_QUARTIC, "ideal_quartic"),
+                              (wl.EOS_TM, wl.C2P_CUBIC, "tm_cubic"), (wl.EOS_TM, wl.C2P_BRENT, "tm_brent")):
+        cfg = wl.make_config("random3d", n_elem=(10, 10, 10), p=2, eos=eos, c2p=method, c=c, precision=wl.FP64)
+        s = Solver(cfg)
+        n = wl.n_dof(cfg)
+        rates, errs, errs10 = [], [], []
+        src = torch.empty(s.shape, dtype=torch.float64, device="cuda")
+        W = s.empty()
+        for g, P in zip(G.ravel(), PP.ravel()):
+            beta = np.sqrt((1 - 1 / g) * (1 + 1 / g))
+            src[0].fill_(1.0 / g)
+            src[1].fill_(beta * c)
+            src[2].zero_()
+            src[3].zero_()
+            src[4].fill_(P)
+            U = s.set_state(src)
+            s.con2prim(U, out=W)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(runs):
+                s.con2prim(U, out=W)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rates.append(n * runs / (e0.elapsed_time(e1) / 1e3))
+            u = W[1:4].reshape(3, -1)[:, 0].double().cpu()
+            ux = float(u[0])
+            v = ux / np.sqrt(1 + float((u * u).sum()) / c ** 2)
+            err = abs(v - beta * c) / (beta * c) if beta > 0 else abs(v)
+            errs.append(err)
+            if g <= 10:
+                errs10.append(err)
+        s.close()
+        r = np.array(rates)
+        out[name] = {"recoveries_per_s_median": float(np.median(r)), "min": float(r.min()), "max": float(r.max()),
+                     "vel_rel_err_max": float(max(errs)), "vel_rel_err_max_gamma_le_10": float(max(errs10))}
+    return {"study": "25x25 (gamma in [1,100], P in [1e5,1e10] Pa), 10^3 cells x 27 points, "
+                     f"{runs} runs per state, c = 3e8 m/s, D = 1", "solvers": out}
+
+
 def cpu_baseline(kind="kh_tm", steps=3):
     """The oracle as it stands, on the host cores, for `steps` SSP-RK3 steps of the full mesh."""
     import torch
@@ -145,6 +221,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="kh_tm")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32, adjoint and CPU legs")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--con2prim-study", action="store_true",
+                    help="only run the recovery-solver study of the paper's Sec. 3.3 and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -157,6 +235,9 @@ def main(argv=None):
     from paper_2205_00095_amd import workloads as wl
 
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if args.con2prim_study:
+        print(json.dumps(con2prim_study()), flush=True)
+        return 0
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -173,6 +254,7 @@ def main(argv=None):
     value = dofs * args.steps * 3 / seconds
     bytes_per_launch = _stage_bytes_per_dof(nvar) * dofs
     achieved = bytes_per_launch / stage_s / 1e9
+    prof = _measured_traffic(args.workload)
     out = {
         "metric": "DG DOF-stage updates/s (FP64 vs FP32-contraction); adjoint/forward cost ratio",
         "value": value,
@@ -195,13 +277,24 @@ def main(argv=None):
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": prof["traffic_bytes_per_launch"] if prof else None,
             "kernel": "k_element stage (one SSP-RK3 stage)",
             "stage_us": stage_s * 1e6, "con2prim_us": t_c2p * 1e6,
             "bytes_per_dof": _stage_bytes_per_dof(nvar),
+            "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "diagnostics": diag,
     }
+    if prof:
+        # executed-instruction view of the same kernel from the counter summary
+        out["roofline"]["traffic_over_algorithmic"] = prof["traffic_bytes_per_launch"] / bytes_per_launch
+        if "valu_insts_per_wave" in prof:
+            waves = dofs / 64.0
+            issue_s = prof["valu_insts_per_wave"] * waves * VALU_CYCLES_PER_WAVE_INST / (SIMDS * CLOCK_HZ)
+            out["roofline"]["valu"] = {
+                "insts_per_dof": prof["valu_insts_per_wave"], "f64_insts_per_dof": prof.get("f64_insts_per_wave"),
+                "issue_bound_us": issue_s * 1e6, "issue_frac": issue_s / stage_s}
     if not args.no_extras and args.workload == "kh_tm":
         extras = {}
         cfg3, s64, U64 = _setup("kh_tm_fp32", precision=wl.FP64)

@@ -28,6 +28,20 @@ FLAGS = [
 ]
 
 
+# sources the forward element kernel is compiled from (with FLAGS): a measurement taken
+# on one build is matched to the current sources through this digest
+ELEMENT_KERNEL_SOURCES = ("kernels.hpp", "physics.hpp", "launch.hip", "launch.hpp")
+
+
+def source_digest(files=ELEMENT_KERNEL_SOURCES) -> str:
+    import hashlib
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def _units():
     units = [("dg_api.hip", "dg_api.o", []), ("adjoint.hip", "adjoint.o", [])]
     for d in (1, 2, 3):

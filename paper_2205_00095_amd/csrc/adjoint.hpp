@@ -67,7 +67,7 @@ __host__ __device__ __forceinline__ void nodal_flux_rev(const double* W, const P
     lam_ig += lam_vd * W[1 + d];
   }
   lamW[NV - 1] += lam_P;
-  eval_state_rev<EOS, DIM>(W, q, lam_U, 0.0, lam_ig, 0.0, 0.0, lamW);
+  eval_state_rev<EOS, DIM>(W, s, q, lam_U, 0.0, lam_ig, 0.0, 0.0, lamW);
 }
 
 // Adjoint of the physicality operator on the elements of one workgroup.  Pn is
@@ -76,12 +76,12 @@ __host__ __device__ __forceinline__ void nodal_flux_rev(const double* W, const P
 // element's argmin node, its stage-1/stage-2 case and the average.  sbuf needs
 // (NV + 1) * NT doubles, sred NV * EPB doubles, sflag NT ints.  All threads of
 // the block must reach it.
-template <int DIM, int P>
+template <int DIM, int P, int NT, int EPB>
 __device__ __forceinline__ void physicality_vjp_block(const double* Pn, double* lam, bool act, int tid, int el,
                                                       int node, const Tables& t, const PhysParams& q, double* sbuf,
                                                       double* sred, int* sflag) {
   using G = Geo<DIM, P>;
-  constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, N1 = G::N1;
+  constexpr int NV = G::NV, NPE = G::NPE, N1 = G::N1;
   const bool bad = act && !admissible<DIM>(Pn, q);
   if (!__syncthreads_or(bad)) return;
   double wn = t.w[node_coord<N1>(node, 0)];
@@ -152,7 +152,7 @@ __device__ __forceinline__ void physicality_vjp_block(const double* Pn, double* 
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         gP[v] = lam_s * sd.t[v];
-        sred[v * G::EPB + el] = lam_s * sd.t[NV + v];
+        sred[v * EPB + el] = lam_s * sd.t[NV + v];
       }
     }
   }
@@ -160,7 +160,7 @@ __device__ __forceinline__ void physicality_vjp_block(const double* Pn, double* 
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double lamUb = (1.0 - smin) * sumlam[v] + sred[v * G::EPB + el];
+      const double lamUb = (1.0 - smin) * sumlam[v] + sred[v * EPB + el];
       double r = smin * lam[v] + wn * t.inv_wsum * lamUb;
       if (node == istar) r += gP[v];
       lam[v] = r;
@@ -190,22 +190,29 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce_vjp(const double*
     Pn[v] = act ? Pst[v * m.ntot + g] : 1.0;
     lam[v] = act ? lam_in[v * m.ntot + g] : 0.0;
   }
-  physicality_vjp_block<DIM, P>(Pn, lam, act, tid, el, node, t, q, sbuf, sred, sflag);
+  physicality_vjp_block<DIM, P, NT, EPB>(Pn, lam, act, tid, el, node, t, q, sbuf, sred, sflag);
   if (act) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) lam_out[v * m.ntot + g] = lam[v];
   }
 }
 
+// Waves per SIMD the adjoint element kernel is compiled for: 3 (at most 168 VGPRs,
+// a few spills) measured faster than 2 for the 2D ideal-gas kernels; elsewhere the
+// spills at 3 would be heavy.
+template <int DIM, int EOS>
+constexpr int vjp_min_waves() { return (DIM == 2 && EOS == EOS_IDEAL) ? 3 : 2; }
+
 template <int DIM, int P, int EOS, int MODE>
-__global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_rhs_vjp(VjpArgs a) {
-  using G = Geo<DIM, P>;
-  constexpr int N1 = G::N1, NPE = G::NPE, NV = G::NV, NT = G::NT, EPB = G::EPB;
-  constexpr int NFP = G::NFP, NF = G::NF, FPB = G::FPB;
+__global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, EOS>())) void k_rhs_vjp(VjpArgs a) {
+  using T = TileGeo<DIM, P>;
+  constexpr int N1 = T::N1, NPE = T::NPE, NV = T::NV, NT = T::NT, EPB = T::EPB;
+  constexpr int NFP = T::NFP, FPB = T::FPB, TX = T::TX, TY = T::TY;
   __shared__ double sW[NV * NT];
   __shared__ double sL[(NV + 1) * NT];
-  __shared__ double sLW[NV * FPB];
-  __shared__ int sfb[FPB];
+  __shared__ double sLWL[NV * FPB];  // adjoint of the left (+) trace of each face point
+  __shared__ double sLWR[NV * FPB];  // adjoint of the right (-) trace
+  __shared__ int sfb[FPB];           // bit 0: left trace fell back, bit 1: right trace fell back
   __shared__ double sred[(MODE == VJP_STAGE) ? NV * EPB : 1];
   __shared__ int sflag[(MODE == VJP_STAGE) ? NT : 1];
 
@@ -215,10 +222,13 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_rhs_vjp(VjpArgs a) {
   const long long ntot = m.ntot;
   const int tid = threadIdx.x;
   const int el = tid / NPE, node = tid % NPE;
-  const int e0 = blockIdx.x * EPB;
-  const int e = e0 + el;
-  const bool act = e < m.nelem;
-  const long long g = (long long)e * NPE + node;
+  const int ntx = (m.nex + TX - 1) / TX, nty = (m.ney + TY - 1) / TY, ntz = (m.nez + T::TZ - 1) / T::TZ;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
+  const int o[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * T::TZ};
+  const int lc[3] = {el % TX, (el / TX) % TY, el / (TX * TY)};
+  const bool act = (o[0] + lc[0] < m.nex) && (o[1] + lc[1] < m.ney) && (o[2] + lc[2] < m.nez);
+  const long long e = act ? ((long long)(o[2] + lc[2]) * m.ney + (o[1] + lc[1])) * m.nex + (o[0] + lc[0]) : 0;
+  const long long g = e * NPE + node;
 
   double W[NV], mu[NV];
 #pragma unroll
@@ -250,76 +260,119 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_rhs_vjp(VjpArgs a) {
     }
     nodal_flux_rev<EOS, DIM>(W, q, lamF, lamW);
   }
+  // end the volume reverse here (the compiler would otherwise sink it past the face
+  // phase and keep every loaded lambda live through it)
+#pragma unroll
+  for (int v = 0; v < NV; ++v) pin_reg(lamW[v]);
 
-  // ---- faces: adjoint of the face flux from both elements' lift transposes; HLL reverse
+  // ---- faces of the tile: adjoint of each face flux from the lift transposes of both
+  //      adjacent elements, HLL linearised once and reversed for every side in the tile
   for (int fp = tid; fp < FPB; fp += NT) {
-    const int fel = fp / (NF * NFP);
-    const int rem = fp - fel * NF * NFP;
-    const int f = rem / NFP;
-    const int pt = rem - f * NFP;
-    const int fe = e0 + fel;
-    if (fe >= m.nelem) continue;
-    const int d = f >> 1;
-    const int side = f & 1;
-    const double* lo = side ? t.lp : t.lm;
-    const double* ln = side ? t.lm : t.lp;
-    const int ob = fel * NPE;
-    double Wo[NV], Wn[NV], lamFh[NV];
+    const TileFacePoint<DIM, P> fc(fp, o, m);
+    const bool left_local = fc.left_local, right_local = fc.right_local;
+    if (!left_local && !right_local) continue;
+    const int d = fc.d, pt = fc.pt;
+    const double tdx = sel3(d, m.two_dx[0], m.two_dx[1], m.two_dx[2]);
+    double WL[NV], WR[NV], lamFh[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lamFh[v] = 0.0;
+    bool have_L = true, have_R = true;
+    int fb = 0;
+    // left element: its + trace; its lift gives -(2/dx) sum_i iw_i lp_i lam_i
+    {
+      const double* srcW = nullptr;
+      const double* srcL = nullptr;
+      long long stride = NT;
+      if (left_local) {
+        const int ob = fc.left_elem() * NPE;
+        srcW = sW + ob;
+        srcL = sL + ob;
+      } else {
+        const long long ge = fc.left_global();
+        have_L = ge >= 0;
+        if (have_L) {
+          srcW = a.W + ge * NPE;
+          srcL = a.lam + ge * NPE;
+          stride = ntot;
+        }
+      }
+      if (have_L) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double acc = 0.0, lacc = 0.0;
+#pragma unroll
+          for (int i = 0; i < N1; ++i) {
+            const int ln_i = line_node<DIM, N1>(d, pt, i);
+            acc += t.lp[i] * srcW[v * stride + ln_i];
+            lacc += t.iw[i] * t.lp[i] * srcL[v * stride + ln_i];
+          }
+          WL[v] = acc;
+          lamFh[v] -= tdx * lacc;
+        }
+        if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
+          fb |= 1;
+          const int nb = line_node<DIM, N1>(d, pt, P);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) WL[v] = srcW[v * stride + nb];
+        }
+      }
+    }
+    // right element: its - trace; its lift gives +(2/dx) sum_i iw_i lm_i lam_i
+    {
+      const double* srcW = nullptr;
+      const double* srcL = nullptr;
+      long long stride = NT;
+      if (right_local) {
+        const int ob = fc.right_elem() * NPE;
+        srcW = sW + ob;
+        srcL = sL + ob;
+      } else {
+        const long long ge = fc.right_global();
+        have_R = ge >= 0;
+        if (have_R) {
+          srcW = a.W + ge * NPE;
+          srcL = a.lam + ge * NPE;
+          stride = ntot;
+        }
+      }
+      if (have_R) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double acc = 0.0, lacc = 0.0;
+#pragma unroll
+          for (int i = 0; i < N1; ++i) {
+            const int ln_i = line_node<DIM, N1>(d, pt, i);
+            acc += t.lm[i] * srcW[v * stride + ln_i];
+            lacc += t.iw[i] * t.lm[i] * srcL[v * stride + ln_i];
+          }
+          WR[v] = acc;
+          lamFh[v] += tdx * lacc;
+        }
+        if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
+          fb |= 2;
+          const int nb = line_node<DIM, N1>(d, pt, 0);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) WR[v] = srcW[v * stride + nb];
+        }
+      }
+    }
+    double lamWL[NV], lamWR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lamWL[v] = lamWR[v] = 0.0;
+    if (!have_L) {
+      // outflow: exterior = the right trace, both HLL arguments are that trace
+      hll_flux_rev<EOS, DIM>(WR, WR, d, q, lamFh, lamWR, lamWR, true, true);
+    } else if (!have_R) {
+      hll_flux_rev<EOS, DIM>(WL, WL, d, q, lamFh, lamWL, lamWL, true, true);
+    } else {
+      hll_flux_rev<EOS, DIM>(WL, WR, d, q, lamFh, lamWL, lamWR, left_local, right_local);
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double acc = 0.0, lacc = 0.0;
-#pragma unroll
-      for (int i = 0; i < N1; ++i) {
-        const int ln_i = line_node<DIM, N1>(d, pt, i);
-        acc += lo[i] * sW[v * NT + ob + ln_i];
-        lacc += t.iw[i] * lo[i] * sL[v * NT + ob + ln_i];
-      }
-      Wo[v] = acc;
-      // own lift: S_i -= (2/dx)(1/w_i)[l_i(+1) Fhat^+ - l_i(-1) Fhat^-]
-      lamFh[v] = (side ? -m.two_dx[d] : m.two_dx[d]) * lacc;
+      sLWL[v * FPB + fp] = lamWL[v];
+      sLWR[v * FPB + fp] = lamWR[v];
     }
-    int fbo = 0;
-    if (!(Wo[0] > 0.0) || !(Wo[NV - 1] > 0.0)) {
-      fbo = 1;
-      const int nb = ob + line_node<DIM, N1>(d, pt, side ? P : 0);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Wo[v] = sW[v * NT + nb];
-    }
-    const int ne = neighbour(m, fe, d, side ? 1 : -1);
-    double lamWo[NV], lamWn[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) lamWo[v] = lamWn[v] = 0.0;
-    if (ne < 0) {
-      hll_flux_rev<EOS, DIM>(Wo, Wo, d, q, lamFh, lamWo, lamWo);
-    } else {
-      const long long nbase = (long long)ne * NPE;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double* srcW = a.W + v * ntot + nbase;
-        const double* srcL = a.lam + v * ntot + nbase;
-        double acc = 0.0, lacc = 0.0;
-#pragma unroll
-        for (int i = 0; i < N1; ++i) {
-          const int ln_i = line_node<DIM, N1>(d, pt, i);
-          acc += ln[i] * srcW[ln_i];
-          lacc += t.iw[i] * ln[i] * srcL[ln_i];
-        }
-        Wn[v] = acc;
-        // the neighbour sees this face from its other side
-        lamFh[v] += (side ? m.two_dx[d] : -m.two_dx[d]) * lacc;
-      }
-      if (!(Wn[0] > 0.0) || !(Wn[NV - 1] > 0.0)) {
-        const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, side ? 0 : P);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Wn[v] = src[v * ntot];
-      }
-      // only this element's side is needed: the neighbour reverses its own side
-      if (side) hll_flux_rev<EOS, DIM>(Wo, Wn, d, q, lamFh, lamWo, lamWn, true, false);
-      else hll_flux_rev<EOS, DIM>(Wn, Wo, d, q, lamFh, lamWn, lamWo, false, true);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sLW[v * FPB + fp] = lamWo[v];
-    sfb[fp] = fbo;
+    sfb[fp] = fb;
   }
   __syncthreads();
 
@@ -328,18 +381,29 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_rhs_vjp(VjpArgs a) {
   for (int d = 0; d < DIM; ++d) {
     const int id = node_coord<N1>(node, d);
     const int pt = face_pt<DIM, N1>(node, d);
+    // minus face: this element is the right side
+    {
+      const int fpi = tile_face_index<DIM, P>(d, lc[d], lc, pt);
+      const double coef = (sfb[fpi] & 2) ? (id == 0 ? 1.0 : 0.0) : t.lm[id];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int fpi = (el * NF + 2 * d + side) * NFP + pt;
-      double coef;
-      if (sfb[fpi]) coef = (id == (side ? P : 0)) ? 1.0 : 0.0;
-      else coef = side ? t.lp[id] : t.lm[id];
+      for (int v = 0; v < NV; ++v) lamW[v] += coef * sLWR[v * FPB + fpi];
+    }
+    // plus face: this element is the left side
+    {
+      const int fpi = tile_face_index<DIM, P>(d, lc[d] + 1, lc, pt);
+      const double coef = (sfb[fpi] & 1) ? (id == P ? 1.0 : 0.0) : t.lp[id];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) lamW[v] += coef * sLW[v * FPB + fpi];
+      for (int v = 0; v < NV; ++v) lamW[v] += coef * sLWL[v * FPB + fpi];
     }
   }
 
-  // ---- recovery adjoint (implicit-function theorem)
+  // ---- recovery adjoint (implicit-function theorem); W and mu come back from LDS so
+  //      they are not held in registers through the face phase
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    W[v] = sW[v * NT + tid];
+    mu[v] = sL[v * NT + tid];
+  }
   double lamU[NV];
   if (is_floor_state<DIM>(W, q)) {
 #pragma unroll
@@ -368,7 +432,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_rhs_vjp(VjpArgs a) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) Pn[v] = act ? a.Pprev[v * ntot + g] : 1.0;
       __syncthreads();
-      physicality_vjp_block<DIM, P>(Pn, lp, act, tid, el, node, t, q, sL, sred, sflag);
+      physicality_vjp_block<DIM, P, NT, EPB>(Pn, lp, act, tid, el, node, t, q, sL, sred, sflag);
       if (act) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {

@@ -340,6 +340,70 @@ __device__ __forceinline__ int tile_face_index(int d, int f, const int* l, int p
   return off + fi * T::NFP + pt;
 }
 
+template <typename X>
+__device__ __forceinline__ X sel3(int d, X a, X b, X c) { return d == 0 ? a : (d == 1 ? b : c); }
+
+// One point of the tile's face-point list, with the addressing of the two elements
+// that share its face (the face lies between local elements f-1 and f along d).
+// Scalar selects rather than small arrays indexed by the per-lane direction, which
+// the compiler would otherwise place in scratch memory.
+template <int DIM, int P>
+struct TileFacePoint {
+  int d, f, pt;
+  int loc0, lstride;        // tile-local element of the face's row at coordinate 0 along d; stride along d
+  long long gbase, gstride; // the same in global element numbering
+  int od, nnd, per;         // tile origin, mesh extent and periodicity along d
+  bool left_local, right_local;
+
+  __device__ __forceinline__ TileFacePoint(int fp, const int* o, const MeshArgs& m) {
+    using T = TileGeo<DIM, P>;
+    int fi, l0, l1, l2;
+    if (fp < T::FOFF1) { d = 0; fi = fp; }
+    else if (DIM > 1 && fp < T::FOFF2) { d = 1; fi = fp - T::FOFF1; }
+    else { d = 2; fi = fp - T::FOFF2; }
+    const int face = fi / T::NFP;
+    pt = fi - face * T::NFP;
+    if (d == 0) {
+      f = face % (T::TX + 1); l1 = (face / (T::TX + 1)) % T::TY; l2 = face / ((T::TX + 1) * T::TY); l0 = 0;
+    } else if (d == 1) {
+      l0 = face % T::TX; f = (face / T::TX) % (T::TY + 1); l2 = face / (T::TX * (T::TY + 1)); l1 = 0;
+    } else {
+      l0 = face % T::TX; l1 = (face / T::TX) % T::TY; f = face / (T::TX * T::TY); l2 = 0;
+    }
+    // the coordinate along d is 0 here and every tile origin lies inside the mesh
+    const bool inside = (o[0] + l0 < m.nex) && (o[1] + l1 < m.ney) && (o[2] + l2 < m.nez);
+    od = sel3(d, o[0], o[1], o[2]);
+    nnd = sel3(d, m.nex, m.ney, m.nez);
+    per = sel3(d, m.periodic[0], m.periodic[1], m.periodic[2]);
+    lstride = sel3(d, 1, T::TX, T::TX * T::TY);
+    loc0 = (l2 * T::TY + l1) * T::TX + l0;
+    gstride = sel3<long long>(d, 1, m.nex, (long long)m.nex * m.ney);
+    gbase = ((long long)(o[2] + l2) * m.ney + (o[1] + l1)) * m.nex + (o[0] + l0) - (long long)od * gstride;
+    const int gl = od + f - 1, gr = od + f;
+    left_local = inside && f >= 1 && gl < nnd;
+    right_local = inside && f <= sel3(d, T::TX, T::TY, T::TZ) - 1 && gr < nnd;
+  }
+  __device__ __forceinline__ int left_elem() const { return loc0 + (f - 1) * lstride; }
+  __device__ __forceinline__ int right_elem() const { return loc0 + f * lstride; }
+  // global element left / right of the face after the periodic wrap, -1 at an outflow boundary
+  __device__ __forceinline__ long long left_global() const {
+    int g = od + f - 1;
+    if (g < 0) {
+      if (!per) return -1;
+      g += nnd;
+    }
+    return gbase + g * gstride;
+  }
+  __device__ __forceinline__ long long right_global() const {
+    int g = od + f;
+    if (g >= nnd) {
+      if (!per) return -1;
+      g -= nnd;
+    }
+    return gbase + g * gstride;
+  }
+};
+
 // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs
 // (hardware block b runs on XCD b % 8), so hardware block b is mapped to logical
 // tile start(x) + b / 8, where XCD x owns the contiguous range of nb/8 (+1 for the
@@ -350,6 +414,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int x = b & 7, k = b >> 3;
   return x * q + min(x, r) + k;
 }
+
+// Materialise a value in registers at this point of the program: its computation
+// cannot be sunk below it (an empty asm that reads and writes the register).
+__device__ __forceinline__ void pin_reg(double& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin_reg(float& x) { asm volatile("" : "+v"(x)); }
 
 #ifndef DG_ELEM_MIN_BLOCKS
 #define DG_ELEM_MIN_BLOCKS 1
@@ -375,7 +444,6 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_e
   const int ntx = (m.nex + TX - 1) / TX, nty = (m.ney + TY - 1) / TY, ntz = (m.nez + TZ - 1) / TZ;
   const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
   const int o[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * TZ};
-  const int nn[3] = {m.nex, m.ney, m.nez};
   const int lc[3] = {el % TX, (el / TX) % TY, el / (TX * TY)};
   const bool act = (o[0] + lc[0] < m.nex) && (o[1] + lc[1] < m.ney) && (o[2] + lc[2] < m.nez);
   const long long e = act ? ((long long)(o[2] + lc[2]) * m.ney + (o[1] + lc[1])) * m.nex + (o[0] + lc[0]) : 0;
@@ -429,123 +497,94 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_e
       }
     }
   }
+  // end the contraction here: left to itself the compiler sinks these FMAs to the
+  // lift and keeps all the loaded fluxes live through the face phase (~70 VGPRs)
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (PREC == PREC_FP64) pin_reg(R[v]);
+    else pin_reg(Rf[v]);
+  }
   __syncthreads();
 
   // ---- faces of the tile: primitive traces (FP64), exterior states, HLL flux per face point
   unsigned nfb = 0;  // trace fallbacks seen by this lane
   for (int fp = tid; fp < FPB; fp += NT) {
-    int d, fi;
-    if (fp < T::FOFF1) { d = 0; fi = fp; }
-    else if (DIM > 1 && fp < T::FOFF2) { d = 1; fi = fp - T::FOFF1; }
-    else { d = 2; fi = fp - T::FOFF2; }
-    const int face = fi / NFP;
-    const int pt = fi - face * NFP;
-    int l[3], f;
-    if (d == 0) {
-      f = face % (TX + 1); l[1] = (face / (TX + 1)) % TY; l[2] = face / ((TX + 1) * TY); l[0] = 0;
-    } else if (d == 1) {
-      l[0] = face % TX; f = (face / TX) % (TY + 1); l[2] = face / (TX * (TY + 1)); l[1] = 0;
-    } else {
-      l[0] = face % TX; l[1] = (face / TX) % TY; f = face / (TX * TY); l[2] = 0;
-    }
-    // the face lies between local elements f-1 and f along d
-    bool other_ok = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if (k != d && o[k] + l[k] >= nn[k]) other_ok = false;
-    const int gl = o[d] + f - 1, gr = o[d] + f;
-    const bool left_local = other_ok && f >= 1 && gl < nn[d];
-    const bool right_local = other_ok && f <= (d == 0 ? TX : d == 1 ? TY : TZ) - 1 && gr < nn[d];
-    if (!left_local && !right_local) continue;
+    const TileFacePoint<DIM, P> fc(fp, o, m);
+    if (!fc.left_local && !fc.right_local) continue;
+    const int d = fc.d, pt = fc.pt;
     double WL[NV], WR[NV];
     bool have_L = true, have_R = true;
     // left state: + trace of the left element
-    {
-      int lcl[3] = {l[0], l[1], l[2]};
-      lcl[d] = f - 1;
-      if (left_local) {
-        const int ob = ((lcl[2] * TY + lcl[1]) * TX + lcl[0]) * NPE;
+    if (fc.left_local) {
+      const int ob = fc.left_elem() * NPE;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
+        WL[v] = acc;
+      }
+      if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
+        const int nb = ob + line_node<DIM, N1>(d, pt, P);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) WL[v] = sW[v * NT + nb];
+        nfb++;
+      }
+    } else {
+      const long long ge = fc.left_global();
+      have_L = ge >= 0;
+      if (have_L) {
+        const long long nbase = ge * NPE;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+          const double* src = a.W + v * ntot + nbase;
           double acc = 0.0;
 #pragma unroll
-          for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
+          for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * src[line_node<DIM, N1>(d, pt, aa)];
           WL[v] = acc;
         }
         if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
-          const int nb = ob + line_node<DIM, N1>(d, pt, P);
+          const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, P);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) WL[v] = sW[v * NT + nb];
+          for (int v = 0; v < NV; ++v) WL[v] = src[v * ntot];
           nfb++;
-        }
-      } else {
-        int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-        gc[d] = gl;
-        if (gc[d] < 0) {
-          if (m.periodic[d]) gc[d] += nn[d];
-          else have_L = false;
-        }
-        if (have_L) {
-          const long long nbase = (((long long)gc[2] * m.ney + gc[1]) * m.nex + gc[0]) * NPE;
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const double* src = a.W + v * ntot + nbase;
-            double acc = 0.0;
-#pragma unroll
-            for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * src[line_node<DIM, N1>(d, pt, aa)];
-            WL[v] = acc;
-          }
-          if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
-            const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, P);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) WL[v] = src[v * ntot];
-            nfb++;
-          }
         }
       }
     }
     // right state: - trace of the right element
-    {
-      int lcl[3] = {l[0], l[1], l[2]};
-      lcl[d] = f;
-      if (right_local) {
-        const int ob = ((lcl[2] * TY + lcl[1]) * TX + lcl[0]) * NPE;
+    if (fc.right_local) {
+      const int ob = fc.right_elem() * NPE;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
+        WR[v] = acc;
+      }
+      if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
+        const int nb = ob + line_node<DIM, N1>(d, pt, 0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) WR[v] = sW[v * NT + nb];
+        nfb++;
+      }
+    } else {
+      const long long ge = fc.right_global();
+      have_R = ge >= 0;
+      if (have_R) {
+        const long long nbase = ge * NPE;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+          const double* src = a.W + v * ntot + nbase;
           double acc = 0.0;
 #pragma unroll
-          for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
+          for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * src[line_node<DIM, N1>(d, pt, aa)];
           WR[v] = acc;
         }
         if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
-          const int nb = ob + line_node<DIM, N1>(d, pt, 0);
+          const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, 0);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) WR[v] = sW[v * NT + nb];
+          for (int v = 0; v < NV; ++v) WR[v] = src[v * ntot];
           nfb++;
-        }
-      } else {
-        int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-        gc[d] = gr;
-        if (gc[d] >= nn[d]) {
-          if (m.periodic[d]) gc[d] -= nn[d];
-          else have_R = false;
-        }
-        if (have_R) {
-          const long long nbase = (((long long)gc[2] * m.ney + gc[1]) * m.nex + gc[0]) * NPE;
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const double* src = a.W + v * ntot + nbase;
-            double acc = 0.0;
-#pragma unroll
-            for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * src[line_node<DIM, N1>(d, pt, aa)];
-            WR[v] = acc;
-          }
-          if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
-            const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, 0);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) WR[v] = src[v * ntot];
-            nfb++;
-          }
         }
       }
     }

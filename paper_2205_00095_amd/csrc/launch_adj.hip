@@ -12,9 +12,10 @@ namespace {
 
 template <int DIM, int P, int EOS, int MODE>
 hipError_t run_vjp(const VjpArgs& a, hipStream_t s) {
-  using G = Geo<DIM, P>;
-  const int nb = (a.m.nelem + G::EPB - 1) / G::EPB;
-  hipLaunchKernelGGL((k_rhs_vjp<DIM, P, EOS, MODE>), dim3(nb), dim3(G::NT), 0, s, a);
+  using T = TileGeo<DIM, P>;
+  const int nb = ((a.m.nex + T::TX - 1) / T::TX) * ((a.m.ney + T::TY - 1) / T::TY) *
+                 ((a.m.nez + T::TZ - 1) / T::TZ);
+  hipLaunchKernelGGL((k_rhs_vjp<DIM, P, EOS, MODE>), dim3(nb), dim3(T::NT), 0, s, a);
   return hipGetLastError();
 }
 

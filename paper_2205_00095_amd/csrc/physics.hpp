@@ -57,6 +57,30 @@ __host__ __device__ __forceinline__ double sound2(double th, double he, const Ph
   }
 }
 
+// Component d of a DIM-vector stored from v[0], for a direction known only at run
+// time: a chain of selects over values.  An indexed access would move the array to
+// scratch memory, and so would the optimiser's folding of a select of two loads into
+// one indexed load, which the empty asm (device pass only) hides the loads from.
+__host__ __device__ __forceinline__ double opaque(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+v"(x));
+#endif
+  return x;
+}
+template <int DIM>
+__host__ __device__ __forceinline__ double comp(const double* v, int d) {
+  double x = opaque(v[0]);
+#pragma unroll
+  for (int j = 1; j < DIM; ++j) x = (d == j) ? opaque(v[j]) : x;
+  return x;
+}
+template <int DIM>
+__host__ __device__ __forceinline__ void comp_add(double* v, int d, double x) {
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+    if (d == j) v[j] += x;
+}
+
 // ------------------------------------------------- state relations (Sec. 2.1)
 // Everything a face or node needs from a primitive state: conserved variables
 // (Eq. primitive_to_conserved) and the pieces shared by fluxes and wavespeeds.
@@ -106,7 +130,7 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
 // energy row minus c^2 times the mass row): (D v_d, S v_d + P e_d, (tau + P) v_d).
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void flux_dir(const double* W, const StateEval<EOS, DIM>& s, int d, double* F) {
-  const double vd = W[1 + d] * s.ig;
+  const double vd = comp<DIM>(W + 1, d) * s.ig;
 #pragma unroll
   for (int k = 0; k < DIM + 2; ++k) F[k] = s.U[k] * vd;
 #pragma unroll
@@ -128,7 +152,7 @@ __host__ __device__ __forceinline__ void wavespeeds(const double* W, const State
     const double th = s.th;
     cs2 = q.c2 * (3.0 * th * th + 5.0 * th * s.sq) / (12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s.sq);
   }
-  const double vd = W[1 + d] * s.ig;
+  const double vd = comp<DIM>(W + 1, d) * s.ig;
   // with den = gamma^2 (c^2 - c_s^2), sigma = c_s^2/den and
   // lambda_pm = (vd den pm sqrt(c_s^2 (den (c^2 - vd^2) + c^2 c_s^2))) / (den + c_s^2)
   const double den = s.g2 * (q.c2 - cs2);

@@ -11,11 +11,11 @@ namespace dgsrhd {
 
 // d(h - c^2)/dTheta
 template <int EOS>
-__host__ __device__ __forceinline__ double h_excess_d(double th, const PhysParams& q) {
+__host__ __device__ __forceinline__ double h_excess_d(double th, const PhysParams& q, double sq = -1.0) {
   if constexpr (EOS == EOS_IDEAL) {
     return q.alpha;
   } else {
-    const double s = sqrt(th * th + (4.0 / 9.0) * q.c4);
+    const double s = sq >= 0.0 ? sq : sqrt(th * th + (4.0 / 9.0) * q.c4);
     const double den = s + (2.0 / 3.0) * q.c2;
     // 5/2 Theta + 3/2 Theta^2 / den,   d den / dTheta = Theta / s
     return 2.5 + 1.5 * (2.0 * th * den - th * th * th / s) / (den * den);
@@ -24,13 +24,13 @@ __host__ __device__ __forceinline__ double h_excess_d(double th, const PhysParam
 
 // d(c_s^2)/dTheta with c_s^2 written as a function of Theta alone
 template <int EOS>
-__host__ __device__ __forceinline__ double sound2_d(double th, const PhysParams& q) {
+__host__ __device__ __forceinline__ double sound2_d(double th, const PhysParams& q, double sq = -1.0) {
   if constexpr (EOS == EOS_IDEAL) {
     // c^2 Gamma Theta / (c^2 + alpha Theta)
     const double den = q.c2 + q.alpha * th;
     return q.c2 * q.gam * q.c2 / (den * den);
   } else {
-    const double s = sqrt(th * th + (4.0 / 9.0) * q.c4);
+    const double s = sq >= 0.0 ? sq : sqrt(th * th + (4.0 / 9.0) * q.c4);
     const double ds = th / s;
     const double num = 3.0 * th * th + 5.0 * th * s;
     const double den = 12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s;
@@ -41,32 +41,33 @@ __host__ __device__ __forceinline__ double sound2_d(double th, const PhysParams&
 }
 
 // Adjoint of eval_state: given adjoints of (U[0..NV), g2, ig, th, he) and of P
-// (returned through lam_W[NV-1]), accumulate into lam_W.
+// (returned through lam_W[NV-1]), accumulate into lam_W.  st is the forward
+// evaluation at W (its square roots and quotients are reused).
 template <int EOS, int DIM>
-__host__ __device__ __forceinline__ void eval_state_rev(const double* W, const PhysParams& q, const double* lam_U,
-                                               double lam_g2, double lam_ig, double lam_th, double lam_he,
-                                               double* lam_W) {
+__host__ __device__ __forceinline__ void eval_state_rev(const double* W, const StateEval<EOS, DIM>& st,
+                                                        const PhysParams& q, const double* lam_U, double lam_g2,
+                                                        double lam_ig, double lam_th, double lam_he, double* lam_W) {
   constexpr int NV = DIM + 2;
   const double rho = W[0];
-  const double P = W[NV - 1];
   double usq = 0.0;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) usq += W[1 + j] * W[1 + j];
-  const double g2 = 1.0 + usq * q.inv_c2;
-  const double g = sqrt(g2);
-  const double th = P / rho;
-  const double he = h_excess<EOS>(th, q);
-  const double D = g * rho;
+  const double g2 = st.g2;
+  const double ig = st.ig;
+  const double g = g2 * ig;
+  const double th = st.th;
+  const double he = st.he;
+  const double D = st.U[0];
   const double hc = (q.c2 + he) * q.inv_c2;
   const double gH = g * rho * hc;
-  const double gp1 = g + 1.0;
+  const double igp1 = 1.0 / (g + 1.0);
   // ig = 1/g
-  double lam_g = -lam_ig / g2;
+  double lam_g = -lam_ig * ig * ig;
   // tau = D usq/(g+1) + g2 rho he - P
   const double lt = lam_U[NV - 1];
-  double lam_D = lam_U[0] + lt * usq / gp1;
-  double lam_usq = lt * D / gp1;
-  lam_g += -lt * D * usq / (gp1 * gp1);
+  double lam_D = lam_U[0] + lt * usq * igp1;
+  double lam_usq = lt * D * igp1;
+  lam_g += -lt * D * usq * igp1 * igp1;
   lam_g2 += lt * rho * he;
   double lam_rho = lt * g2 * he;
   lam_he += lt * g2 * rho;
@@ -86,12 +87,13 @@ __host__ __device__ __forceinline__ void eval_state_rev(const double* W, const P
   lam_g += lam_D * rho;
   lam_rho += lam_D * g;
   // he = h_excess(th)
-  lam_th += lam_he * h_excess_d<EOS>(th, q);
+  lam_th += lam_he * h_excess_d<EOS>(th, q, st.sq);
   // th = P / rho
-  lam_P += lam_th / rho;
-  lam_rho += -lam_th * th / rho;
+  const double irho = 1.0 / rho;
+  lam_P += lam_th * irho;
+  lam_rho += -lam_th * th * irho;
   // g = sqrt(g2)
-  lam_g2 += lam_g / (2.0 * g);
+  lam_g2 += lam_g * 0.5 * ig;
   // g2 = 1 + usq/c^2
   lam_usq += lam_g2 * q.inv_c2;
 #pragma unroll
@@ -100,17 +102,25 @@ __host__ __device__ __forceinline__ void eval_state_rev(const double* W, const P
   lam_W[NV - 1] += lam_P;
 }
 
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void eval_state_rev(const double* W, const PhysParams& q, const double* lam_U,
+                                                        double lam_g2, double lam_ig, double lam_th, double lam_he,
+                                                        double* lam_W) {
+  StateEval<EOS, DIM> st;
+  eval_state<EOS, DIM>(W, q, st);
+  eval_state_rev<EOS, DIM>(W, st, q, lam_U, lam_g2, lam_ig, lam_th, lam_he, lam_W);
+}
+
 // Adjoint of (U, F^d, lambda_-, lambda_+) of one primitive state along d.
 // lam_U, lam_F: adjoints of the conserved state and of the flux; lam_lm, lam_lp:
 // adjoints of the two signal speeds (pass 0 when unused).
 template <int EOS, int DIM>
-__host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, int d, const PhysParams& q,
-                                                     const double* lam_U_in, const double* lam_F, double lam_lm,
-                                                     double lam_lp, bool with_speeds, double* lam_W) {
+__host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, const StateEval<EOS, DIM>& s, int d,
+                                                              const PhysParams& q, const double* lam_U_in,
+                                                              const double* lam_F, double lam_lm, double lam_lp,
+                                                              bool with_speeds, double* lam_W) {
   constexpr int NV = DIM + 2;
-  StateEval<EOS, DIM> s;
-  eval_state<EOS, DIM>(W, q, s);
-  const double vd = W[1 + d] * s.ig;
+  const double vd = comp<DIM>(W + 1, d) * s.ig;
   double lam_U[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) lam_U[k] = lam_U_in[k];
@@ -121,11 +131,17 @@ __host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, i
     lam_U[k] += lam_F[k] * vd;
     lam_vd += lam_F[k] * s.U[k];
   }
-  double lam_P = lam_F[1 + d] + lam_F[NV - 1] * vd;
+  double lam_P = comp<DIM>(lam_F + 1, d) + lam_F[NV - 1] * vd;
   lam_vd += lam_F[NV - 1] * s.P;
   double lam_g2 = 0.0, lam_th = 0.0;
   if (with_speeds) {
-    const double cs2 = sound2<EOS>(s.th, s.he, q);
+    double cs2;
+    if constexpr (EOS == EOS_IDEAL) {
+      cs2 = q.c2 * q.gam * s.th / (q.c2 + s.he);
+    } else {
+      const double th = s.th;
+      cs2 = q.c2 * (3.0 * th * th + 5.0 * th * s.sq) / (12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s.sq);
+    }
     const double den = q.c2 - cs2;
     const double sigma = cs2 / (s.g2 * den);
     const double Qr = q.c2 - vd * vd + q.c2 * sigma;
@@ -145,13 +161,23 @@ __host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, i
     // sigma = cs2 / (g2 (c^2 - cs2))
     const double lam_cs2 = lam_sigma * q.c2 / (s.g2 * den * den);
     lam_g2 += -lam_sigma * sigma / s.g2;
-    lam_th += lam_cs2 * sound2_d<EOS>(s.th, q);
+    lam_th += lam_cs2 * sound2_d<EOS>(s.th, q, s.sq);
   }
   // vd = u_d * ig
-  lam_W[1 + d] += lam_vd * s.ig;
-  const double lam_ig = lam_vd * W[1 + d];
+  comp_add<DIM>(lam_W + 1, d, lam_vd * s.ig);
+  const double lam_ig = lam_vd * comp<DIM>(W + 1, d);
   lam_W[NV - 1] += lam_P;
-  eval_state_rev<EOS, DIM>(W, q, lam_U, lam_g2, lam_ig, lam_th, 0.0, lam_W);
+  eval_state_rev<EOS, DIM>(W, s, q, lam_U, lam_g2, lam_ig, lam_th, 0.0, lam_W);
+}
+
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, int d, const PhysParams& q,
+                                                              const double* lam_U_in, const double* lam_F,
+                                                              double lam_lm, double lam_lp, bool with_speeds,
+                                                              double* lam_W) {
+  StateEval<EOS, DIM> s;
+  eval_state<EOS, DIM>(W, q, s);
+  state_flux_speed_rev<EOS, DIM>(W, s, d, q, lam_U_in, lam_F, lam_lm, lam_lp, with_speeds, lam_W);
 }
 
 // Adjoint of hll_flux(WL, WR, d): accumulates into lam_WL and lam_WR.
@@ -200,8 +226,8 @@ __host__ __device__ __forceinline__ void hll_flux_rev(const double* WL, const do
     if (lmL <= lmR) lam_lmL = lam_aL; else lam_lmR = lam_aL;
     if (lpL >= lpR) lam_lpL = lam_aR; else lam_lpR = lam_aR;
   }
-  if (need_L) state_flux_speed_rev<EOS, DIM>(WL, d, q, lam_UL, lam_FL, lam_lmL, lam_lpL, speeds, lam_WL);
-  if (need_R) state_flux_speed_rev<EOS, DIM>(WR, d, q, lam_UR, lam_FR, lam_lmR, lam_lpR, speeds, lam_WR);
+  if (need_L) state_flux_speed_rev<EOS, DIM>(WL, sL, d, q, lam_UL, lam_FL, lam_lmL, lam_lpL, speeds, lam_WL);
+  if (need_R) state_flux_speed_rev<EOS, DIM>(WR, sR, d, q, lam_UR, lam_FR, lam_lmR, lam_lpR, speeds, lam_WR);
 }
 
 // J[r][c] = dU_r / dW_c at the primitive state W (Eq. primitive_to_conserved).
