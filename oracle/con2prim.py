@@ -244,7 +244,9 @@ def con2prim(U, st, method=None):
         return ideal_newton(U, st)
     if st.eos == IDEAL and m == QUARTIC:
         return ideal_quartic(U, st)
-    if st.eos == TM and m == CUBIC:
+    if st.eos == TM and m in (CUBIC, NEWTON):
+        # Newton on the TM cubic (Sec. 3) converges to the same root the analytic
+        # formula gives; the defined result is that root
         return tm_cubic(U, st)
     if st.eos == TM and m == BRENT:
         return tm_brent(U, st)

@@ -212,11 +212,11 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   if (d.eos != DG_EOS_IDEAL && d.eos != DG_EOS_TM) return bad("unknown eos");
   if (d.eos == DG_EOS_IDEAL && !(d.gamma_ad > 1.0)) return bad("gamma_ad must exceed 1");
   if (!(d.c_light > 0.0)) return bad("c_light must be positive");
-  if (d.c2p == DG_C2P_DEFAULT) d.c2p = (d.eos == DG_EOS_IDEAL) ? DG_C2P_NEWTON : DG_C2P_CUBIC;
+  if (d.c2p == DG_C2P_DEFAULT) d.c2p = DG_C2P_NEWTON;
   if (d.eos == DG_EOS_IDEAL && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_QUARTIC)
     return bad("ideal EOS needs the Newton or quartic solver");
-  if (d.eos == DG_EOS_TM && d.c2p != DG_C2P_CUBIC && d.c2p != DG_C2P_BRENT)
-    return bad("TM EOS needs the cubic or Brent solver");
+  if (d.eos == DG_EOS_TM && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_CUBIC && d.c2p != DG_C2P_BRENT)
+    return bad("TM EOS needs the Newton, cubic or Brent solver");
   if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT) return bad("unknown precision");
   if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
   const long long nelem = (long long)d.n_elem[0] * d.n_elem[1] * d.n_elem[2];

@@ -660,7 +660,10 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_e
       for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = Un[v];
       if (a.Wout) {
         double Wn[NV];
-        const int st = con2prim<EOS, DIM>(Un, Wn, q);
+        double Wp[NV];  // this node's primitives at the start of the stage (Newton start)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Wp[v] = sW[v * NT + tid];
+        const int st = con2prim<EOS, DIM>(Un, Wn, q, Wp);
         count_c2p(a.cnt, st, e);
 #pragma unroll
         for (int v = 0; v < NV; ++v) a.Wout[v * ntot + g] = Wn[v];

@@ -272,8 +272,14 @@ __host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, dou
 // Conserved -> primitive at one node with the configured solver.  Returns a C2P_*
 // status; on failure writes the floor state.  Also returns the pieces the
 // implicit-function-theorem adjoint needs through the primitive output only.
+// Wprev, when given, is the node's primitive state of the previous SSP-RK stage: with
+// the TM EOS and C2P_NEWTON it starts three Newton steps on the cubic, accepted when
+// the last step is below 1e-9 W and the iterate lies on the branch of the largest
+// root (f' > 0 beyond the inflection point); otherwise, and without Wprev, the
+// analytic root with one Newton polish.  Both give the same root to rounding.
 template <int EOS, int DIM>
-__host__ __device__ __forceinline__ int con2prim(const double* U, double* W, const PhysParams& q) {
+__host__ __device__ __forceinline__ int con2prim(const double* U, double* W, const PhysParams& q,
+                                                 const double* Wprev = nullptr) {
   constexpr int NV = DIM + 2;
   const double D = U[0];
   const double tau = U[NV - 1];
@@ -377,21 +383,43 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
           if (!tm_brent_root(c1, c2, c3, 0.0, hi, Wc)) status = C2P_NOCONV;
         }
       } else {
-        // analytic (trigonometric / Cardano), then one Newton step on the cubic
-        const double Q = (3.0 * c2 - c1 * c1) * (1.0 / 9.0);
-        const double R = (9.0 * c1 * c2 - 27.0 * c3 - 2.0 * c1 * c1 * c1) * (1.0 / 54.0);
-        const double dd = Q * Q * Q + R * R;
-        if (dd < 0.0) {
-          double arg = R * rsqrt(-Q * Q * Q);
-          arg = fmin(1.0, fmax(-1.0, arg));
-          Wc = 2.0 * sqrt(-Q) * cos(acos(arg) * (1.0 / 3.0)) - c1 * (1.0 / 3.0);
-        } else {
-          const double sd = sqrt(dd);
-          Wc = -c1 * (1.0 / 3.0) + cube_root(R + sd) + cube_root(R - sd);
+        bool done = false;
+        if (method == C2P_NEWTON && Wprev != nullptr) {
+          double u2 = 0.0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) u2 += Wprev[1 + j] * Wprev[1 + j];
+          double Wn = u2 * q.inv_c2;  // gamma^2 - 1 of the previous stage
+          double step = 0.0;
+#pragma unroll
+          for (int it = 0; it < 3; ++it) {
+            const double f = ((Wn + c1) * Wn + c2) * Wn + c3;
+            const double fp = (3.0 * Wn + 2.0 * c1) * Wn + c2;
+            step = f / fp;
+            Wn -= step;
+          }
+          const double fp = (3.0 * Wn + 2.0 * c1) * Wn + c2;
+          if (fabs(step) <= 1e-9 * fabs(Wn) && fp > 0.0 && 3.0 * Wn + c1 > 0.0) {
+            Wc = Wn;
+            done = true;
+          }
         }
-        const double f = ((Wc + c1) * Wc + c2) * Wc + c3;
-        const double fp = (3.0 * Wc + 2.0 * c1) * Wc + c2;
-        Wc = Wc - f / fp;
+        if (!done) {
+          // analytic (trigonometric / Cardano), then one Newton step on the cubic
+          const double Q = (3.0 * c2 - c1 * c1) * (1.0 / 9.0);
+          const double R = (9.0 * c1 * c2 - 27.0 * c3 - 2.0 * c1 * c1 * c1) * (1.0 / 54.0);
+          const double dd = Q * Q * Q + R * R;
+          if (dd < 0.0) {
+            double arg = R * rsqrt(-Q * Q * Q);
+            arg = fmin(1.0, fmax(-1.0, arg));
+            Wc = 2.0 * sqrt(-Q) * cos(acos(arg) * (1.0 / 3.0)) - c1 * (1.0 / 3.0);
+          } else {
+            const double sd = sqrt(dd);
+            Wc = -c1 * (1.0 / 3.0) + cube_root(R + sd) + cube_root(R - sd);
+          }
+          const double f = ((Wc + c1) * Wc + c2) * Wc + c3;
+          const double fp = (3.0 * Wc + 2.0 * c1) * Wc + c2;
+          Wc = Wc - f / fp;
+        }
       }
       Wc = fmax(Wc, 0.0);
       const double gam = sqrt(1.0 + Wc);

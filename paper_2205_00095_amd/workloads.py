@@ -64,7 +64,7 @@ def make_config(kind: str, **over) -> dict:
         n = {"kh_tm": 256, "kh_tm_fp32": 512, "kh_ideal": 128}[kind]
         cfg = dict(dim=2, p=3, n_elem=(n, n, 1), lo=(0.0, -1.0, 0.0), hi=(1.0, 1.0, 1.0),
                    bc=(PERIODIC, OUTFLOW, PERIODIC), eos=EOS_TM, gamma_ad=4.0 / 3.0,
-                   c=1.0, c2p=C2P_CUBIC, precision=FP64, phys=True, steps=100, init="kh")
+                   c=1.0, c2p=C2P_NEWTON, precision=FP64, phys=True, steps=100, init="kh")
         if kind == "kh_tm_fp32":
             cfg.update(precision=FP32_CONTRACT, steps=50)
         if kind == "kh_ideal":

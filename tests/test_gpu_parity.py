@@ -186,6 +186,8 @@ def test_enforce_matches_oracle(dim, p, n_elem):
 
 
 @pytest.mark.parametrize("kind,over,nsteps", [("kh_tm", {"n_elem": (12, 10, 1)}, 1),
+                                              ("kh_tm", {"n_elem": (12, 10, 1)}, 4),
+                                              ("kh_tm", {"n_elem": (12, 10, 1), "c2p": wl.C2P_CUBIC}, 4),
                                               ("kh_ideal", {"n_elem": (10, 9, 1)}, 5),
                                               ("wave1d", {}, 10),
                                               ("random3d", {"n_elem": (5, 4, 3)}, 1)])
@@ -206,3 +208,22 @@ def test_ssprk3_steps_match_oracle(kind, over, nsteps):
     assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
     if kind == "random3d":
         assert s.diagnostics()["smoothed"] == stats.get("smoothed", 0)
+
+
+@pytest.mark.parametrize("dt_scale", [30.0, 300.0])
+def test_tm_newton_start_far_from_root(dt_scale):
+    """Steps so large that the previous stage's primitives are a poor Newton start for
+    the TM cubic: the recovery must still return the oracle's root (the start is
+    accepted only when converged on the physical root)."""
+    cfg = wl.make_config("kh_tm", n_elem=(9, 8, 1), c2p=wl.C2P_NEWTON)
+    st, U = oracle_state(cfg)
+    dt = cfg["dt"] * dt_scale
+    U_ref = ots.step(U, dt, st)
+    tol, sens = parity_tol(lambda V: ots.step(V, dt, st), U)
+    s = _solver(cfg, sync=False)
+    Ud = U.cuda().contiguous()
+    s.step(Ud, dt)
+    err = rel_err_per_var(Ud.cpu(), U_ref)
+    print(f"dt x{dt_scale}: err {err.tolist()} tol {tol.tolist()}", flush=True)
+    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    assert s.diagnostics()["c2p_fail"] == 0
