@@ -88,6 +88,43 @@ def _time_con2prim(solver, U, reps=20):
     return t0.elapsed_time(t1) / 1e3 / reps
 
 
+def _time_rhs(solver, U, reps=20):
+    """dg_rhs alone: recovery launch + element kernel in RHS mode."""
+    import torch
+    R = solver.empty()
+    solver.rhs(U, out=R)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        solver.rhs(U, out=R)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / 1e3 / reps
+
+
+def _copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) of a 1 GiB buffer."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    rate = 2.0 * nbytes * reps / (t0.elapsed_time(t1) / 1e3)
+    del src, dst
+    return rate
+
+
 def _setup(kind, **over):
     import torch
     from paper_2205_00095_amd import workloads as wl
@@ -189,8 +226,35 @@ def con2prim_study(runs=100):
         r = np.array(rates)
         out[name] = {"recoveries_per_s_median": float(np.median(r)), "min": float(r.min()), "max": float(r.max()),
                      "vel_rel_err_max": float(max(errs)), "vel_rel_err_max_gamma_le_10": float(max(errs10))}
+        # the same 625 states tiled over a 64^3 p=2 mesh (7,077,888 points): one launch is
+        # then long enough that the rate is the solver's, not the launch latency's
+        big = wl.make_config("random3d", p=2, eos=eos, c2p=method, c=c, precision=wl.FP64)
+        sb = Solver(big)
+        nb = wl.n_dof(big)
+        srcb = torch.empty(sb.shape, dtype=torch.float64, device="cuda").reshape(5, -1)
+        gi = torch.arange(nb, device="cuda") % G.size
+        gam = torch.from_numpy(G.ravel()).cuda()[gi]
+        srcb[0] = 1.0 / gam
+        srcb[1] = torch.sqrt((1 - 1 / gam) * (1 + 1 / gam)) * c
+        srcb[2].zero_()
+        srcb[3].zero_()
+        srcb[4] = torch.from_numpy(PP.ravel()).cuda()[gi]
+        Ub = sb.set_state(srcb.reshape(sb.shape))
+        Wb = sb.empty()
+        sb.con2prim(Ub, out=Wb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            sb.con2prim(Ub, out=Wb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name]["recoveries_per_s_7M_points"] = nb * 20 / (e0.elapsed_time(e1) / 1e3)
+        sb.close()
+        del srcb, Ub, Wb
     return {"study": "25x25 (gamma in [1,100], P in [1e5,1e10] Pa), 10^3 cells x 27 points, "
-                     f"{runs} runs per state, c = 3e8 m/s, D = 1", "solvers": out}
+                     f"{runs} runs per state, c = 3e8 m/s, D = 1; also all 625 states tiled over 7.08M points",
+            "solvers": out}
 
 
 def cpu_baseline(kind="kh_tm", steps=3):
@@ -249,6 +313,7 @@ def main(argv=None):
     nvar = cfg["dim"] + 2
     seconds = _time_run(solver, U, cfg["dt"], args.steps, args.warmup)
     t_c2p = _time_con2prim(solver, U)
+    t_rhs = _time_rhs(solver, U)
     stage_s = max(seconds - t_c2p, 1e-12) / (3 * args.steps)
     diag = solver.diagnostics()
     value = dofs * args.steps * 3 / seconds
@@ -285,6 +350,11 @@ def main(argv=None):
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "diagnostics": diag,
+        "dg_rhs": {
+            "us": t_rhs * 1e6, "algorithmic_bytes": 2 * nvar * 8.0 * dofs,
+            "achieved_GBs": 2 * nvar * 8.0 * dofs / t_rhs / 1e9,
+            "frac": 2 * nvar * 8.0 * dofs / t_rhs / 1e9 / HBM_PEAK_GBS,
+            "note": "recovery launch + element kernel in RHS mode; read U, write R"},
     }
     if prof:
         # executed-instruction view of the same kernel from the counter summary
@@ -299,16 +369,31 @@ def main(argv=None):
         extras = {}
         cfg3, s64, U64 = _setup("kh_tm_fp32", precision=wl.FP64)
         n3 = min(args.steps, 50)
+        U0 = U64.clone()
+        R64 = s64.rhs(U0)
         t64 = _time_run(s64, U64, cfg3["dt"], n3, 5)
+        V64 = U0.clone()
+        s64.run(V64, cfg3["dt"], n3)
         del s64, U64
         cfg3, s32, U32 = _setup("kh_tm_fp32")
+        R32 = s32.rhs(U0)
         t32 = _time_run(s32, U32, cfg3["dt"], n3, 5)
+        V32 = U0.clone()
+        s32.run(V32, cfg3["dt"], n3)
         d3 = wl.n_dof(cfg3)
+        nv3 = R64.shape[0]
+        rhs_err = ((R32 - R64).reshape(nv3, -1).abs().max(1).values /
+                   R64.reshape(nv3, -1).abs().max(1).values).max().item()
+        drift = ((V32 - V64).reshape(nv3, -1).abs().sum(1) / V64.reshape(nv3, -1).abs().sum(1)).max().item()
         extras["fp32_contract"] = {
             "workload": "kh_tm_fp32: 2D 512x512 elements p=3 TM EOS",
             "value_fp32": d3 * n3 * 3 / t32, "value_fp64": d3 * n3 * 3 / t64,
-            "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": n3}
-        del s32, U32
+            "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": n3,
+            "rhs_rel_err_vs_fp64": rhs_err, "l1_drift_vs_fp64_after_steps": drift,
+            "note": "errors against the FP64 GPU path on the same input (that path matches the FP64 oracle "
+                    "to 1e-12 in the parity tests); max over conserved variables"}
+        del s32, U32, R64, R32, V64, V32, U0
+        extras["hbm_copy_GBs"] = _copy_bandwidth() / 1e9
         extras["adjoint"] = adjoint_ratio()
         out.update(extras)
         out["cpu_baseline"] = cpu_baseline("kh_tm", args.cpu_steps)
