@@ -14,6 +14,8 @@ physicality operator on.  Extra results on the same JSON line:
                  20) relative to the forward run, 128x128 p=2 ideal-gas mesh;
   roofline       the stage kernel against HBM, from algorithmic bytes per
                  DOF-stage (read U^(k), read U^n in stages 2-3, write U^(k+1)).
+  paper_sweep    the paper's KH performance grid: p = 0, 1, 2 with RK1, SSPRK2,
+                 SSPRK3 on 256x512 .. 1024x2048 meshes (ideal EOS).
   cpu_baseline   the FP64 CPU oracle on the host cores for a bounded sample.
 """
 from __future__ import annotations
@@ -257,6 +259,70 @@ def con2prim_study(runs=100):
             "solvers": out}
 
 
+def paper_sweep(target_s=0.15):
+    """The paper's KH performance grid (Sec. 4) on one MI355X: basis orders 0, 1, 2 with
+    RK1, SSPRK2, SSPRK3 on nx x 2nx meshes, nx = 256, 512, 1024 (ideal EOS, HLL)."""
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    rows = []
+    for p in (0, 1, 2):
+        for nx in (256, 512, 1024):
+            cfg, solver, U = _setup("kh_paper", nx=nx, p=p)
+            order = cfg["rk_order"]
+            dofs = wl.n_dof(cfg)
+            solver.run(U, cfg["dt"], 3, order=order)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solver.run(U, cfg["dt"], 5, order=order)
+            torch.cuda.synchronize()
+            per_step = (time.perf_counter() - t0) / 5
+            n = max(10, int(target_s / per_step))
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            solver.run(U, cfg["dt"], n, order=order)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3
+            rows.append({"p": p, "rk_order": order, "mesh": f"{nx}x{2 * nx}", "dof": dofs, "steps": n,
+                         "dof_stage_per_s": dofs * n * order / sec, "stage_us": sec / (n * order) * 1e6})
+            solver.close()
+            del U
+    return {"workload": "kh_paper: one shear interface, ideal Gamma=4/3, HLL, physicality operator on, FP64",
+            "rows": rows}
+
+
+def kh_growth(nx=256, orders=(0, 1, 2), t_end=3.0, sample_dt=0.05):
+    """Growth rate r of <v_y^2> from a least-squares fit of log <v_y^2> = A + r t over
+    t in [1.5, 3] (the paper's KH diagnostic, Sec. 4), per basis order on an nx x 2nx mesh."""
+    import numpy as np
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    out = []
+    for p in orders:
+        cfg, solver, U = _setup("kh_paper", nx=nx, p=p)
+        order, dt = cfg["rk_order"], cfg["dt"]
+        area = (cfg["hi"][0] - cfg["lo"][0]) * (cfg["hi"][1] - cfg["lo"][1])
+        every = max(1, int(round(sample_dt / dt)))
+        ts, vals = [0.0], [solver.objective_vy2(U) / area]
+        t = 0.0
+        t0 = time.perf_counter()
+        while t < t_end - 1e-12:
+            solver.run(U, dt, every, order=order)
+            t += every * dt
+            ts.append(t)
+            vals.append(solver.objective_vy2(U) / area)
+        wall = time.perf_counter() - t0
+        ts, vals = np.array(ts), np.array(vals)
+        sel = (ts >= 1.5) & (ts <= 3.0)
+        r, A = np.polyfit(ts[sel], np.log(vals[sel]), 1)
+        out.append({"p": p, "rk_order": order, "mesh": f"{nx}x{2 * nx}", "dof": wl.n_dof(cfg),
+                    "growth_rate": float(r), "vy2_t0": float(vals[0]), "vy2_t3": float(vals[sel][-1]),
+                    "steps": int(round(t / dt)), "wall_s": wall, "diagnostics": solver.diagnostics()})
+        solver.close()
+    return {"diagnostic": "fit of log <v_y^2> = A + r t over t in [1.5, 3]", "rows": out}
+
+
 def cpu_baseline(kind="kh_tm", steps=3):
     """The oracle as it stands, on the host cores, for `steps` SSP-RK3 steps of the full mesh."""
     import torch
@@ -287,6 +353,8 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--con2prim-study", action="store_true",
                     help="only run the recovery-solver study of the paper's Sec. 3.3 and print its JSON")
+    ap.add_argument("--kh-growth", action="store_true",
+                    help="only run the KH growth-rate diagnostic of the paper's Sec. 4 and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -301,6 +369,9 @@ def main(argv=None):
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     if args.con2prim_study:
         print(json.dumps(con2prim_study()), flush=True)
+        return 0
+    if args.kh_growth:
+        print(json.dumps(kh_growth()), flush=True)
         return 0
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -394,6 +465,7 @@ def main(argv=None):
                     "to 1e-12 in the parity tests); max over conserved variables"}
         del s32, U32, R64, R32, V64, V32, U0
         extras["hbm_copy_GBs"] = _copy_bandwidth() / 1e9
+        extras["paper_sweep"] = paper_sweep()
         extras["adjoint"] = adjoint_ratio()
         out.update(extras)
         out["cpu_baseline"] = cpu_baseline("kh_tm", args.cpu_steps)

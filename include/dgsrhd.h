@@ -129,6 +129,16 @@ int dg_ssprk3_step(dg_ctx* ctx, double* U_dev, double dt);
 /* nsteps such steps (the primitive state is carried between steps). */
 int dg_ssprk3_run(dg_ctx* ctx, double* U_dev, double dt, int nsteps);
 
+/* One step (nsteps steps) of the SSP Runge-Kutta scheme of the given order in
+ * Shu-Osher form (Sec. 2.3; the paper pairs basis orders p = 0, 1, 2 with
+ * orders 1, 2, 3 in its convergence and performance runs): order 1 forward Euler,
+ * 2 the second-order SSP scheme U1 = U + dt L(U), U+ = U/2 + (U1 + dt L(U1))/2,
+ * 3 the scheme of dg_ssprk3_step.  In place on U_dev, the physicality operator
+ * after each stage when desc.phys = 1, one kernel launch per stage.  Returns
+ * DG_EINVAL for order outside 1..3 or nsteps < 0. */
+int dg_ssprk_step(dg_ctx* ctx, double* U_dev, double dt, int order);
+int dg_ssprk_run(dg_ctx* ctx, double* U_dev, double dt, int nsteps, int order);
+
 /* Vector-Jacobian product of dg_rhs: lamU_dev = (dR/dU)^T lamR_dev.  The
  * recovery is differentiated by the implicit-function theorem.  The buffers
  * must not overlap. */

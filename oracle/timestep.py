@@ -8,9 +8,15 @@ Reading: the paper does not place the operator; it is applied after every
 stage, so each stage stays a convex combination of admissible forward-Euler
 states.  The step is fixed: dt = 0.1/(2p+1) min_d dx_d / c.
 
-Pinned by tests/test_oracle_timestep.py: third-order convergence in time on
-a scalar ODE with a known solution, and (test_oracle_convergence.py) the
-full scheme on the exact translated density wave.
+Lower orders (the paper pairs basis orders 0, 1, 2 with RK1, SSPRK2, SSPRK3 in
+its convergence and performance runs, Sec. 2.3 citing the Shu-Osher schemes):
+RK1 is forward Euler, U^+ = Pi(U + dt L(U)); SSPRK2 is
+U1 = Pi(U + dt L(U)), U^+ = Pi(1/2 U + 1/2 (U1 + dt L(U1))).
+
+Pinned by tests/test_oracle_timestep.py: one step of each scheme on a linear
+ODE equals the Taylor polynomial of its order; the observed order on a
+nonlinear ODE; and the full scheme's convergence on the exact translated
+density wave (p = 2 with SSPRK3; p = 0 with RK1 and p = 1 with SSPRK2).
 """
 from __future__ import annotations
 
@@ -23,14 +29,27 @@ def ssprk3(U, dt, L, P=lambda v: v):
     return P(U / 3.0 + (2.0 / 3.0) * (U2 + dt * L(U2)))
 
 
-def step(U, dt, st, phys=True, stats=None):
+def rk1(U, dt, L, P=lambda v: v):
+    return P(U + dt * L(U))
+
+
+def ssprk2(U, dt, L, P=lambda v: v):
+    U1 = P(U + dt * L(U))
+    return P(0.5 * U + 0.5 * (U1 + dt * L(U1)))
+
+
+SCHEMES = {1: rk1, 2: ssprk2, 3: ssprk3}
+
+
+def step(U, dt, st, phys=True, stats=None, order=3):
     L = lambda V: dg.rhs(V, st, stats)  # noqa: E731
+    scheme = SCHEMES[order]
     if phys:
-        return ssprk3(U, dt, L, lambda V: physicality.enforce(V, st, stats))
-    return ssprk3(U, dt, L)
+        return scheme(U, dt, L, lambda V: physicality.enforce(V, st, stats))
+    return scheme(U, dt, L)
 
 
-def run(U, dt, nsteps, st, phys=True, stats=None):
+def run(U, dt, nsteps, st, phys=True, stats=None, order=3):
     for _ in range(nsteps):
-        U = step(U, dt, st, phys, stats)
+        U = step(U, dt, st, phys, stats, order)
     return U

@@ -51,6 +51,8 @@ SIGNATURES = {
     "dg_enforce_physical": (_I, [_P, _P]),
     "dg_ssprk3_step": (_I, [_P, _P, _D]),
     "dg_ssprk3_run": (_I, [_P, _P, _D, _I]),
+    "dg_ssprk_step": (_I, [_P, _P, _D, _I]),
+    "dg_ssprk_run": (_I, [_P, _P, _D, _I, _I]),
     "dg_rhs_vjp": (_I, [_P, _P, _P, _P]),
     "dg_ssprk3_step_vjp": (_I, [_P, _P, _D, _P, _P]),
     "dg_tape_size": (ctypes.c_size_t, [_P]),

@@ -327,38 +327,61 @@ int dg_enforce_physical(dg_ctx* c, double* U) {
   return finish(c, "dg_enforce_physical");
 }
 
-static int ssprk3_steps(dg_ctx* c, double* U, double dt, int nsteps, const char* what) {
+// SSP Runge-Kutta steps in Shu-Osher form (Sec. 2.3): every stage is
+// U^(k+1) = Pi(ca U^n + cb (U^(k) + dt L(U^(k)))), one fused launch per stage.
+// order 1: forward Euler; 2: the second-order SSP scheme (1/2, 1/2);
+// 3: the third-order SSP scheme (3/4, 1/4; 1/3, 2/3).
+static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, const char* what) {
   if (!c) return DG_EINVAL;
   if (!U) return fail(c, DG_EINVAL, "%s: null pointer", what);
   if (nsteps < 0) return fail(c, DG_EINVAL, "%s: nsteps < 0", what);
+  if (order < 1 || order > 3) return fail(c, DG_EINVAL, "%s: order must be 1, 2 or 3", what);
   if (!std::isfinite(dt)) return fail(c, DG_EINVAL, "%s: dt not finite", what);
   if (nsteps == 0) return DG_OK;
+  struct Stage {
+    double ca, cb;
+    double* in;
+    double* out;
+  };
+  const Stage tab1[1] = {{0.0, 1.0, U, U}};
+  const Stage tab2[2] = {{0.0, 1.0, U, c->U1}, {0.5, 0.5, c->U1, U}};
+  const Stage tab3[3] = {{0.0, 1.0, U, c->U1}, {0.75, 0.25, c->U1, c->U2}, {1.0 / 3.0, 2.0 / 3.0, c->U2, U}};
+  const Stage* tab = order == 1 ? tab1 : (order == 2 ? tab2 : tab3);
   double* Wa = c->Wa;
   double* Wb = c->Wb;
   int r = hipcheck(c, L_con2prim(c, U, Wa), what);
   if (r) return r;
   for (int s = 0; s < nsteps; ++s) {
-    ElemArgs a = base_args(c);
-    a.dt = dt;
-    // stage 1: U1 = Pi(U + dt L(U))
-    a.W = Wa; a.Uk = U; a.Un = U; a.ca = 0.0; a.cb = 1.0; a.out = c->U1; a.Wout = Wb;
-    if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
-    // stage 2: U2 = Pi(3/4 U + 1/4 (U1 + dt L(U1)))
-    a.W = Wb; a.Uk = c->U1; a.ca = 0.75; a.cb = 0.25; a.out = c->U2; a.Wout = Wa;
-    if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
-    // stage 3: U = Pi(1/3 U + 2/3 (U2 + dt L(U2))), in place
-    const bool last = (s == nsteps - 1);
-    a.W = Wa; a.Uk = c->U2; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.out = U; a.Wout = last ? nullptr : Wb;
-    if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
-    double* tmp = Wa; Wa = Wb; Wb = tmp;
+    for (int k = 0; k < order; ++k) {
+      ElemArgs a = base_args(c);
+      a.dt = dt;
+      a.W = Wa;
+      a.Uk = tab[k].in;
+      a.Un = U;
+      a.ca = tab[k].ca;
+      a.cb = tab[k].cb;
+      a.out = tab[k].out;
+      const bool last = (s == nsteps - 1) && (k == order - 1);
+      a.Wout = last ? nullptr : Wb;
+      if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+      double* tmp = Wa; Wa = Wb; Wb = tmp;
+    }
   }
   return finish(c, what);
 }
 
-int dg_ssprk3_step(dg_ctx* c, double* U, double dt) { return ssprk3_steps(c, U, dt, 1, "dg_ssprk3_step"); }
+int dg_ssprk3_step(dg_ctx* c, double* U, double dt) { return ssprk_steps(c, U, dt, 1, 3, "dg_ssprk3_step"); }
 
 int dg_ssprk3_run(dg_ctx* c, double* U, double dt, int nsteps) {
-  return ssprk3_steps(c, U, dt, nsteps, "dg_ssprk3_run");
+  return ssprk_steps(c, U, dt, nsteps, 3, "dg_ssprk3_run");
+}
+
+int dg_ssprk_step(dg_ctx* c, double* U, double dt, int order) {
+  return ssprk_steps(c, U, dt, 1, order, "dg_ssprk_step");
+}
+
+int dg_ssprk_run(dg_ctx* c, double* U, double dt, int nsteps, int order) {
+  return ssprk_steps(c, U, dt, nsteps, order, "dg_ssprk_run");
 }
 
 int dg_get_diagnostics(dg_ctx* c, dg_diag* out) {

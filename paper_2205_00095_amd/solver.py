@@ -108,15 +108,24 @@ class Solver:
         self._check(self.lib.dg_enforce_physical(self.ctx, self._ptr(U, "U")), "dg_enforce_physical")
         return U
 
-    def step(self, U: torch.Tensor, dt: float):
+    def step(self, U: torch.Tensor, dt: float, order: int = 3):
+        """One SSP-RK step of the given order (1, 2, 3) in place on U."""
         self._sync_stream()
-        self._check(self.lib.dg_ssprk3_step(self.ctx, self._ptr(U, "U"), float(dt)), "dg_ssprk3_step")
+        if order == 3:
+            self._check(self.lib.dg_ssprk3_step(self.ctx, self._ptr(U, "U"), float(dt)), "dg_ssprk3_step")
+        else:
+            self._check(self.lib.dg_ssprk_step(self.ctx, self._ptr(U, "U"), float(dt), int(order)), "dg_ssprk_step")
         return U
 
-    def run(self, U: torch.Tensor, dt: float, nsteps: int):
+    def run(self, U: torch.Tensor, dt: float, nsteps: int, order: int = 3):
+        """nsteps SSP-RK steps of the given order (1, 2, 3) in place on U."""
         self._sync_stream()
-        self._check(self.lib.dg_ssprk3_run(self.ctx, self._ptr(U, "U"), float(dt), int(nsteps)),
-                    "dg_ssprk3_run")
+        if order == 3:
+            self._check(self.lib.dg_ssprk3_run(self.ctx, self._ptr(U, "U"), float(dt), int(nsteps)),
+                        "dg_ssprk3_run")
+        else:
+            self._check(self.lib.dg_ssprk_run(self.ctx, self._ptr(U, "U"), float(dt), int(nsteps), int(order)),
+                        "dg_ssprk_run")
         return U
 
     def rhs_vjp(self, U: torch.Tensor, lamR: torch.Tensor, out: torch.Tensor | None = None):

@@ -52,6 +52,10 @@ def make_config(kind: str, **over) -> dict:
                       FP32 contractions, 50 steps.
       ``kh_ideal``    2D KH, ideal Gamma=4/3, 128x128 elements, p=2, FP64,
                       200 steps (the adjoint workload).
+      ``kh_paper``    the paper's KH performance setup (Sec. 4): one shear
+                      interface on [-0.5,0.5]x[-1,1], nx x 2nx elements
+                      (``nx=`` keyword, default 256), ideal Gamma=4/3, p from
+                      the keyword (default 2) with the RK order p+1.
       ``random3d``    3D periodic 64^3 elements, p=2, ideal Gamma=4/3,
                       FP32 contractions, physicality operator on, 20 steps.
     Keyword overrides replace entries (e.g. ``n_elem=(8, 8, 1)``).
@@ -69,6 +73,13 @@ def make_config(kind: str, **over) -> dict:
             cfg.update(precision=FP32_CONTRACT, steps=50)
         if kind == "kh_ideal":
             cfg.update(p=2, eos=EOS_IDEAL, c2p=C2P_NEWTON, steps=200, init="kh_adjoint")
+    elif kind == "kh_paper":
+        nx = over.pop("nx", 256)
+        p = over.get("p", 2)
+        cfg = dict(dim=2, p=p, n_elem=(nx, 2 * nx, 1), lo=(-0.5, -1.0, 0.0), hi=(0.5, 1.0, 1.0),
+                   bc=(PERIODIC, OUTFLOW, PERIODIC), eos=EOS_IDEAL, gamma_ad=4.0 / 3.0,
+                   c=1.0, c2p=C2P_NEWTON, precision=FP64, phys=True, steps=100, init="kh_paper",
+                   rk_order=min(p + 1, 3))
     elif kind == "random3d":
         cfg = dict(dim=3, p=2, n_elem=(64, 64, 64), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                    bc=(PERIODIC, PERIODIC, PERIODIC), eos=EOS_IDEAL, gamma_ad=4.0 / 3.0,
@@ -163,6 +174,21 @@ def kh_primitives(cfg: dict, seed: int = 2):
     return rho, v, P
 
 
+def kh_paper_primitives(cfg: dict):
+    """One smooth relativistic shear interface at y = 0 (the paper's KH setup of
+    its Sec. 4 with the unprinted profile read as):
+    rho = 1, P = c^2, v_x = 0.25 c tanh(y / 0.01),
+    v_y = 0.05 * 0.25 c sin(2 pi x) exp(-y^2 / 0.01)."""
+    x, y, _ = node_coords(cfg)
+    c = cfg["c"]
+    rho = np.ones_like(x)
+    v = np.zeros((cfg["dim"],) + x.shape)
+    v[0] = 0.25 * c * np.tanh(y / 0.01)
+    v[1] = 0.05 * 0.25 * c * np.sin(2.0 * np.pi * x) * np.exp(-y * y / 0.01)
+    P = np.full_like(x, c * c)
+    return rho, v, P
+
+
 def kh_perturbation(cfg: dict, seed: int = 4, sigma: float = 1e-3):
     """Seeded Gaussian per-node perturbation of the initial v_y (sigma = 1e-3 c)."""
     rng = np.random.default_rng(seed)
@@ -201,6 +227,8 @@ def initial_primitives(cfg: dict, seed: int | None = None):
         return kh_primitives(cfg, seed=2 if seed is None else seed)
     if init == "random3d":
         return random3d_primitives(cfg, seed=5 if seed is None else seed)
+    if init == "kh_paper":
+        return kh_paper_primitives(cfg)
     raise ValueError(f"unknown init {init!r}")
 
 

@@ -227,3 +227,28 @@ def test_tm_newton_start_far_from_root(dt_scale):
     print(f"dt x{dt_scale}: err {err.tolist()} tol {tol.tolist()}", flush=True)
     assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
     assert s.diagnostics()["c2p_fail"] == 0
+
+
+@pytest.mark.parametrize("kind,over,nsteps,order", [("kh_tm", {"n_elem": (12, 10, 1), "p": 0}, 6, 1),
+                                                    ("kh_ideal", {"n_elem": (10, 9, 1), "p": 1}, 4, 2),
+                                                    ("wave1d", {"p": 0, "n_elem": (37, 1, 1)}, 10, 1),
+                                                    ("wave1d", {"p": 1}, 10, 2),
+                                                    ("random3d", {"n_elem": (4, 3, 3), "p": 1}, 1, 2),
+                                                    ("kh_paper", {"nx": 8, "p": 0}, 5, 1),
+                                                    ("kh_paper", {"nx": 6, "p": 1}, 3, 2),
+                                                    ("kh_paper", {"nx": 5, "p": 2}, 2, 3)])
+def test_lower_order_ssprk_matches_oracle(kind, over, nsteps, order):
+    """RK1 and SSPRK2 (the paper's pairings with p = 0 and p = 1) against the oracle."""
+    cfg = _case_cfg(kind, over)
+    st, U = oracle_state(cfg)
+    U_ref = ots.run(U, cfg["dt"], nsteps, st, phys=True, order=order)
+    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], nsteps, st, phys=True, order=order), U)
+    s = _solver(cfg, sync=False)
+    Ud = U.cuda().contiguous()
+    if nsteps == 1:
+        s.step(Ud, cfg["dt"], order=order)
+    else:
+        s.run(Ud, cfg["dt"], nsteps, order=order)
+    err = rel_err_per_var(Ud.cpu(), U_ref)
+    print(f"order {order}: err {err.tolist()} tol {tol.tolist()}", flush=True)
+    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())

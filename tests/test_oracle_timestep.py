@@ -17,6 +17,39 @@ def test_linear_ode_step_is_third_order_taylor():
         assert abs(float(y) - (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-15
 
 
+def test_linear_ode_step_lower_orders_taylor():
+    """RK1 and SSPRK2 multiply by 1 + z and 1 + z + z^2/2 on L(y) = lam y."""
+    for z in (0.1, -0.37, 1.3):
+        y1 = timestep.rk1(torch.tensor([1.0]), z, lambda v: v)
+        y2 = timestep.ssprk2(torch.tensor([1.0]), z, lambda v: v)
+        assert abs(float(y1) - (1 + z)) < 1e-15
+        assert abs(float(y2) - (1 + z + z * z / 2)) < 1e-15
+
+
+@pytest.mark.parametrize("order,lo", [(1, 0.95), (2, 1.9)])
+def test_nonlinear_ode_lower_orders(order, lo):
+    def L(Y):
+        return torch.stack([-Y[0] ** 2 + torch.cos(Y[1]), torch.ones_like(Y[1])])
+
+    def solve(n):
+        Y = torch.tensor([1.0, 0.0])
+        for _ in range(n):
+            Y = timestep.SCHEMES[order](Y, 1.0 / n, L)
+        return float(Y[0])
+
+    ref = solve_ref(L)
+    e = [abs(solve(n) - ref) for n in (64, 128, 256)]
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(orders) > lo, orders
+
+
+def solve_ref(L, n=8192):
+    Y = torch.tensor([1.0, 0.0])
+    for _ in range(n):
+        Y = timestep.ssprk3(Y, 1.0 / n, L)
+    return float(Y[0])
+
+
 def test_nonlinear_ode_order_three():
     """y' = -y^2 + cos t folded into an autonomous system; order from three step sizes."""
     def L(Y):
@@ -34,15 +67,15 @@ def test_nonlinear_ode_order_three():
     assert min(orders) > 2.8
 
 
-def _l1_density_error(N):
-    cfg = wl.make_config("wave1d", n_elem=(N, 1, 1))
+def _l1_density_error(N, p=2, order=3):
+    cfg = wl.make_config("wave1d", n_elem=(N, 1, 1), p=p)
     st = Setup.from_config(cfg)
     conv = lambda a: torch.tensor(a)  # noqa: E731
     U = srhd.prim3_to_cons(*(conv(a) for a in wl.initial_primitives(cfg)), st)
     U = U.reshape((3,) + wl.field_shape(cfg))
     tfinal = 0.03125
     n = int(round(tfinal / cfg["dt"]))
-    U = timestep.run(U, cfg["dt"], n, st)
+    U = timestep.run(U, cfg["dt"], n, st, order=order)
     Ue = srhd.prim3_to_cons(*(conv(a) for a in wl.wave1d_primitives(cfg, t=n * cfg["dt"])), st)
     from oracle import basis
     w = torch.tensor(basis.tables(cfg["p"])["w"])
@@ -56,3 +89,11 @@ def test_density_wave_converges_at_order_p_plus_1():
     o1 = math.log2(errs[16] / errs[32])
     o2 = math.log2(errs[32] / errs[64])
     assert o2 > 2.8 and o1 > 2.5, (errs, o1, o2)
+
+
+@pytest.mark.parametrize("p,order,Ns,lo", [(0, 1, (64, 128, 256), 0.98), (1, 2, (32, 64, 128), 1.9)])
+def test_density_wave_lower_orders(p, order, Ns, lo):
+    """The paper's pairings (p = 0, RK1) and (p = 1, SSPRK2) converge at orders 1 and 2."""
+    errs = [_l1_density_error(N, p, order) for N in Ns]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(orders) > lo, (errs, orders)
