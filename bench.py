@@ -259,6 +259,30 @@ def con2prim_study(runs=100):
             "solvers": out}
 
 
+def other_configs():
+    """The remaining named workloads, timed as configured: the 3D stress field (64^3 p=2,
+    FP32 contractions, the physicality operator active) and the 1D density wave (64
+    elements, launch-bound, informational)."""
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    out = {}
+    for kind, warm in (("random3d", 2), ("wave1d", 10)):
+        cfg, solver, U = _setup(kind)
+        n = cfg["steps"]
+        solver.reset_diagnostics()
+        sec = _time_run(solver, U, cfg["dt"], n, warm)
+        d = solver.diagnostics()
+        dofs = wl.n_dof(cfg)
+        stages = 3 * (n + warm)
+        out[kind] = {"dof": dofs, "steps": n, "dof_stage_per_s": dofs * n * 3 / sec, "stage_us": sec / (3 * n) * 1e6,
+                     "precision": "fp32-contraction" if cfg["precision"] == wl.FP32_CONTRACT else "fp64",
+                     "per_stage": {k: d[k] / stages for k in ("smoothed", "flagged", "trace_fallback", "c2p_fail",
+                                                            "bad_average")}}
+        solver.close()
+        del U
+    return out
+
+
 def paper_sweep(target_s=0.15):
     """The paper's KH performance grid (Sec. 4) on one MI355X: basis orders 0, 1, 2 with
     RK1, SSPRK2, SSPRK3 on nx x 2nx meshes, nx = 256, 512, 1024 (ideal EOS, HLL)."""
@@ -466,6 +490,7 @@ def main(argv=None):
         del s32, U32, R64, R32, V64, V32, U0
         extras["hbm_copy_GBs"] = _copy_bandwidth() / 1e9
         extras["paper_sweep"] = paper_sweep()
+        extras["other_configs"] = other_configs()
         extras["adjoint"] = adjoint_ratio()
         out.update(extras)
         out["cpu_baseline"] = cpu_baseline("kh_tm", args.cpu_steps)

@@ -17,11 +17,33 @@ using namespace dgsrhd;
 
 namespace dgsrhd {
 __global__ void k_reset_counters(Counters* cnt) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    cnt->c2p_fail = cnt->c2p_noconv = cnt->trace_fallback = 0ull;
-    cnt->flagged = cnt->smoothed = cnt->bad_average = cnt->bad_input = 0ull;
-    cnt->first_bad = ~0ull;
+  const int i = threadIdx.x;
+  if (i < kCounterSlots) {
+    Counters* c = cnt + i;
+    c->c2p_fail = c->c2p_noconv = c->trace_fallback = 0ull;
+    c->flagged = c->smoothed = c->bad_average = c->bad_input = 0ull;
+    c->first_bad = ~0ull;
   }
+}
+
+// All slots summed (first_bad: the minimum); synchronous.
+static hipError_t read_counters(const dg_ctx* c, Counters& out) {
+  Counters h[kCounterSlots];
+  hipError_t e = hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost);
+  out = Counters{};
+  out.first_bad = ~0ull;
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < kCounterSlots; ++i) {
+    out.c2p_fail += h[i].c2p_fail;
+    out.c2p_noconv += h[i].c2p_noconv;
+    out.trace_fallback += h[i].trace_fallback;
+    out.flagged += h[i].flagged;
+    out.smoothed += h[i].smoothed;
+    out.bad_average += h[i].bad_average;
+    out.bad_input += h[i].bad_input;
+    out.first_bad = h[i].first_bad < out.first_bad ? h[i].first_bad : out.first_bad;
+  }
+  return hipSuccess;
 }
 
 }  // namespace dgsrhd
@@ -169,7 +191,7 @@ int finish(dg_ctx* c, const char* what) {
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
   Counters now{};
-  e = hipMemcpy(&now, c->cnt, sizeof(Counters), hipMemcpyDeviceToHost);
+  e = read_counters(c, now);
   if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
   const Counters prev = c->last;
   c->last = now;
@@ -254,13 +276,13 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   if (e == hipSuccess) e = hipMalloc((void**)&c->Wb, bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->U1, bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->U2, bytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->cnt, sizeof(Counters));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->cnt, sizeof(Counters) * kCounterSlots);
   if (e != hipSuccess) {
     std::fprintf(stderr, "dg_init_mesh: allocation failed: %s\n", hipGetErrorString(e));
     dg_destroy(c);
     return DG_ENOMEM;
   }
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, c->stream, c->cnt);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(kCounterSlots), 0, c->stream, c->cnt);
   e = hipGetLastError();
   if (e != hipSuccess) {
     std::fprintf(stderr, "dg_init_mesh: %s\n", hipGetErrorString(e));
@@ -390,7 +412,7 @@ int dg_get_diagnostics(dg_ctx* c, dg_diag* out) {
   int r = hipcheck(c, hipStreamSynchronize(c->stream), "dg_get_diagnostics");
   if (r) return r;
   Counters h{};
-  r = hipcheck(c, hipMemcpy(&h, c->cnt, sizeof(Counters), hipMemcpyDeviceToHost), "dg_get_diagnostics");
+  r = hipcheck(c, read_counters(c, h), "dg_get_diagnostics");
   if (r) return r;
   out->c2p_fail = (long long)h.c2p_fail;
   out->c2p_noconv = (long long)h.c2p_noconv;
@@ -405,7 +427,7 @@ int dg_get_diagnostics(dg_ctx* c, dg_diag* out) {
 
 int dg_reset_diagnostics(dg_ctx* c) {
   if (!c) return DG_EINVAL;
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, c->stream, c->cnt);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(kCounterSlots), 0, c->stream, c->cnt);
   int r = hipcheck(c, hipGetLastError(), "dg_reset_diagnostics");
   if (r) return r;
   c->last = Counters{};

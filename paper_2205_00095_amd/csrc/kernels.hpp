@@ -51,10 +51,20 @@ struct MeshArgs {
   int periodic[3];
 };
 
+// Event counters, one 64-byte set per slot.  A workgroup counts into slot
+// blockIdx.x mod kCounterSlots: device-scope atomics from every XCD on one cache
+// line serialise (on failure-heavy data that cost milliseconds per stage); the
+// host sums the slots (minimum for first_bad) when it reads them.
 struct Counters {
   unsigned long long c2p_fail, c2p_noconv, trace_fallback, flagged, smoothed, bad_average, bad_input;
   unsigned long long first_bad;  // lowest failing element (ULLONG_MAX if none)
 };
+static_assert(sizeof(Counters) == 64, "one cache line per slot");
+constexpr int kCounterSlots = 256;
+
+__device__ __forceinline__ Counters* counter_slot(Counters* base) {
+  return base + (blockIdx.x & (kCounterSlots - 1));
+}
 
 struct ElemArgs {
   const double* W;    // primitives of the stage input
@@ -144,7 +154,7 @@ __global__ __launch_bounds__(256) void k_con2prim(const double* __restrict__ U, 
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[v * ntot + n];
   const int st = con2prim<EOS, DIM>(u, w, q);
-  count_c2p(cnt, st, n / npe);
+  count_c2p(counter_slot(cnt), st, n / npe);
 #pragma unroll
   for (int v = 0; v < NV; ++v) W[v * ntot + n] = w[v];
 }
@@ -179,7 +189,7 @@ __global__ __launch_bounds__(256) void k_prim3_to_cons(const double* __restrict_
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = 0.0;
   }
-  count_wave(&cnt->bad_input, !ok);
+  count_wave(&counter_slot(cnt)->bad_input, !ok);
 #pragma unroll
   for (int v = 0; v < NV; ++v) U[v * ntot + n] = out[v];
 }
@@ -231,13 +241,13 @@ __device__ __forceinline__ double node_factor(const double* Ui, const double* Ub
 // node's U in registers (act = it belongs to a real element); sbuf must hold
 // NV * NT doubles and sflag NT ints.  Must be reached by all threads of the block.
 template <int DIM, int P, int NTB>
-__device__ __forceinline__ void physicality_block_t(double* Un, bool act, int tid, int el, int node,
+__device__ __forceinline__ bool physicality_block_t(double* Un, bool act, int tid, int el, int node,
                                                   const Tables& t, const PhysParams& q, Counters* cnt,
                                                   double* sbuf, int* sflag) {
   using G = Geo<DIM, P>;
   constexpr int NV = G::NV, NPE = G::NPE, NT = NTB, N1 = G::N1;
   const bool bad = act && !admissible<DIM>(Un, q);
-  if (!__syncthreads_or(bad)) return;
+  if (!__syncthreads_or(bad)) return false;
   double wn = t.w[node_coord<N1>(node, 0)];
   if (DIM > 1) wn *= t.w[node_coord<N1>(node, 1)];
   if (DIM > 2) wn *= t.w[node_coord<N1>(node, 2)];
@@ -274,6 +284,7 @@ __device__ __forceinline__ void physicality_block_t(double* Un, bool act, int ti
     for (int v = 0; v < NV; ++v) Un[v] = smin * Un[v] + (1.0 - smin) * Ub[v];
   }
   __syncthreads();
+  return true;
 }
 
 template <int DIM, int P>
@@ -291,7 +302,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
   double u[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = act ? U[v * m.ntot + g] : 1.0;
-  physicality_block_t<DIM, P, NT>(u, act, tid, el, node, t, q, cnt, sbuf, sflag);
+  physicality_block_t<DIM, P, NT>(u, act, tid, el, node, t, q, counter_slot(cnt), sbuf, sflag);
   if (act) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) U[v * m.ntot + g] = u[v];
@@ -606,7 +617,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_e
     unsigned long long w = nfb;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
-    if ((tid & 63) == 0 && w != 0ull) atomicAdd(&a.cnt->trace_fallback, w);
+    if ((tid & 63) == 0 && w != 0ull) atomicAdd(&counter_slot(a.cnt)->trace_fallback, w);
   }
 
   // ---- lift: S_i = -sum_d (2/dx_d)(1/w_{i_d}) [l_{i_d}(+1) Fhat^+ - l_{i_d}(-1) Fhat^-]
@@ -651,9 +662,12 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_e
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.Pout[v * ntot + g] = Un[v];
     }
+    // true when the operator ran on this tile; otherwise every node passed its
+    // admissibility test and the recovery need not repeat it
+    bool changed = true;
     if (a.phys) {
       __syncthreads();
-      physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, a.cnt, sF, sflag);
+      changed = physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag);
     }
     if (act) {
 #pragma unroll
@@ -663,8 +677,8 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_e
         double Wp[NV];  // this node's primitives at the start of the stage (Newton start)
 #pragma unroll
         for (int v = 0; v < NV; ++v) Wp[v] = sW[v * NT + tid];
-        const int st = con2prim<EOS, DIM>(Un, Wn, q, Wp);
-        count_c2p(a.cnt, st, e);
+        const int st = con2prim<EOS, DIM>(Un, Wn, q, Wp, !changed);
+        count_c2p(counter_slot(a.cnt), st, e);
 #pragma unroll
         for (int v = 0; v < NV; ++v) a.Wout[v * ntot + g] = Wn[v];
       }

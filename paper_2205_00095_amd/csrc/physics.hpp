@@ -277,20 +277,26 @@ __host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, dou
 // the last step is below 1e-9 W and the iterate lies on the branch of the largest
 // root (f' > 0 beyond the inflection point); otherwise, and without Wprev, the
 // analytic root with one Newton polish.  Both give the same root to rounding.
+// known_admissible: the caller has evaluated admissible<DIM>(U) (the same expression)
+// and it held, so the test is skipped.
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, const PhysParams& q,
-                                                 const double* Wprev = nullptr) {
+                                                 const double* Wprev = nullptr, bool known_admissible = false) {
   constexpr int NV = DIM + 2;
   const double D = U[0];
   const double tau = U[NV - 1];
   double s2 = 0.0;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) s2 += U[1 + j] * U[1 + j];
-  const double s2c = s2 * q.inv_c2;
-  const double qq = tau * q.inv_c2 - s2c / (D + sqrt(D * D + s2c));
+  bool ok = known_admissible;
+  if (!ok) {
+    const double s2c = s2 * q.inv_c2;
+    const double qq = tau * q.inv_c2 - s2c / (D + sqrt(D * D + s2c));
+    ok = (D > 0.0) && (qq > 0.0);
+  }
   int status = C2P_OK;
   double rho = kRhoFloor, P = kPFloor * q.c2, gb = 0.0, Smag = 0.0;
-  if (!(D > 0.0) || !(qq > 0.0)) {
+  if (!ok) {
     status = C2P_INADMISSIBLE;
   } else {
     Smag = sqrt(s2);
