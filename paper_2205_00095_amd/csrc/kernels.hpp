@@ -431,11 +431,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 __device__ __forceinline__ void pin_reg(double& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void pin_reg(float& x) { asm volatile("" : "+v"(x)); }
 
-#ifndef DG_ELEM_MIN_BLOCKS
-#define DG_ELEM_MIN_BLOCKS 1
-#endif
+// Waves per SIMD the element kernel is compiled for: the 2D p >= 2 kernels sit a
+// few VGPRs above the 96 that 5 waves allow, and bounded to 96 they spill at most
+// four registers; elsewhere the compiler's allocation stands (a bound spills
+// heavily, or LDS limits the occupancy anyway).
+template <int DIM, int P>
+constexpr int elem_min_waves() { return (DIM == 2 && P >= 2) ? 5 : 1; }
+
 template <int DIM, int P, int EOS, int PREC, int MODE>
-__global__ __launch_bounds__((TileGeo<DIM, P>::NT), DG_ELEM_MIN_BLOCKS) void k_element(ElemArgs a) {
+__global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) void k_element(ElemArgs a) {
   using T = TileGeo<DIM, P>;
   constexpr int N1 = T::N1, NPE = T::NPE, NV = T::NV, NT = T::NT, EPB = T::EPB;
   constexpr int NFP = T::NFP, FPB = T::FPB, TX = T::TX, TY = T::TY, TZ = T::TZ;

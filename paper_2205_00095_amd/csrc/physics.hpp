@@ -61,6 +61,16 @@ __host__ __device__ __forceinline__ double sound2(double th, double he, const Ph
 // time: a chain of selects over values.  An indexed access would move the array to
 // scratch memory, and so would the optimiser's folding of a select of two loads into
 // one indexed load, which the empty asm (device pass only) hides the loads from.
+// 1 / sqrt(x): the device's reciprocal square root (one refined v_rsq), the plain
+// quotient on the host
+__host__ __device__ __forceinline__ double inv_sqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return rsqrt(x);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
 __host__ __device__ __forceinline__ double opaque(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   asm("" : "+v"(x));
@@ -101,9 +111,11 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
 #pragma unroll
   for (int j = 0; j < DIM; ++j) usq += W[1 + j] * W[1 + j];
   const double g2 = 1.0 + usq * q.inv_c2;
-  const double ig = 1.0 / sqrt(g2);
+  const double ig = inv_sqrt(g2);
   const double g = g2 * ig;
-  const double th = P / rho;
+  // one reciprocal for Theta = P / rho and for 1 / (gamma + 1) in tau
+  const double r = 1.0 / (rho * (g + 1.0));
+  const double th = P * (g + 1.0) * r;
   double he;
   if constexpr (EOS == EOS_IDEAL) {
     he = q.alpha * th;
@@ -118,7 +130,7 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
 #pragma unroll
   for (int j = 0; j < DIM; ++j) s.U[1 + j] = gH * W[1 + j];
   // tau = gamma^2 rho h - P - D c^2 = D |u|^2/(gamma+1) + gamma^2 rho (h - c^2) - P
-  s.U[DIM + 1] = D * usq / (g + 1.0) + g2 * rho * he - P;
+  s.U[DIM + 1] = D * usq * (rho * r) + g2 * rho * he - P;
   s.g2 = g2;
   s.ig = ig;
   s.P = P;
@@ -415,7 +427,7 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
           const double R = (9.0 * c1 * c2 - 27.0 * c3 - 2.0 * c1 * c1 * c1) * (1.0 / 54.0);
           const double dd = Q * Q * Q + R * R;
           if (dd < 0.0) {
-            double arg = R * rsqrt(-Q * Q * Q);
+            double arg = R * inv_sqrt(-Q * Q * Q);
             arg = fmin(1.0, fmax(-1.0, arg));
             Wc = 2.0 * sqrt(-Q) * cos(acos(arg) * (1.0 / 3.0)) - c1 * (1.0 / 3.0);
           } else {
