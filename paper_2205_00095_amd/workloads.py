@@ -56,6 +56,9 @@ def make_config(kind: str, **over) -> dict:
                       interface on [-0.5,0.5]x[-1,1], nx x 2nx elements
                       (``nx=`` keyword, default 256), ideal Gamma=4/3, p from
                       the keyword (default 2) with the RK order p+1.
+      ``sound``       a small-amplitude sound wave at rest on the periodic unit
+                      square/cube (``dim=`` 1, 2 or 3, wave vector 2 pi (1,..,1)),
+                      ideal Gamma=4/3: the linear-wave convergence test.
       ``random3d``    3D periodic 64^3 elements, p=2, ideal Gamma=4/3,
                       FP32 contractions, physicality operator on, 20 steps.
     Keyword overrides replace entries (e.g. ``n_elem=(8, 8, 1)``).
@@ -80,6 +83,11 @@ def make_config(kind: str, **over) -> dict:
                    bc=(PERIODIC, OUTFLOW, PERIODIC), eos=EOS_IDEAL, gamma_ad=4.0 / 3.0,
                    c=1.0, c2p=C2P_NEWTON, precision=FP64, phys=True, steps=100, init="kh_paper",
                    rk_order=min(p + 1, 3))
+    elif kind == "sound":
+        dim = over.get("dim", 1)
+        cfg = dict(dim=dim, p=2, n_elem=(16, 16 if dim > 1 else 1, 16 if dim > 2 else 1), lo=(0.0, 0.0, 0.0),
+                   hi=(1.0, 1.0, 1.0), bc=(PERIODIC, PERIODIC, PERIODIC), eos=EOS_IDEAL, gamma_ad=4.0 / 3.0,
+                   c=1.0, c2p=C2P_NEWTON, precision=FP64, phys=True, steps=100, init="sound")
     elif kind == "random3d":
         cfg = dict(dim=3, p=2, n_elem=(64, 64, 64), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                    bc=(PERIODIC, PERIODIC, PERIODIC), eos=EOS_IDEAL, gamma_ad=4.0 / 3.0,
@@ -189,6 +197,39 @@ def kh_paper_primitives(cfg: dict):
     return rho, v, P
 
 
+def sound_primitives(cfg: dict, t: float = 0.0, amp: float = 1e-6):
+    """Right-going acoustic eigenvector of special-relativistic hydrodynamics
+    linearised about rest (rho0 = 1, P0 = 1, c = 1, ideal gas): with
+    cs^2 = Gamma P0 / (rho0 h0), h0 = 1 + Gamma/(Gamma-1) P0/rho0 and phase
+    phi = k.x - |k| cs t, the exact linear solution is
+    v = amp sin(phi) k/|k|,  P = P0 + rho0 h0 cs amp sin(phi),
+    rho = rho0 + rho0 amp sin(phi) / cs.
+    One period later it returns to the initial state; its deviation from the
+    nonlinear solution is O(amp^2)."""
+    coords = node_coords(cfg)
+    dim = cfg["dim"]
+    gam = cfg["gamma_ad"]
+    rho0, P0 = 1.0, 1.0
+    h0 = 1.0 + gam / (gam - 1.0) * P0 / rho0
+    cs = np.sqrt(gam * P0 / (rho0 * h0))
+    k = np.full(dim, 2.0 * np.pi)
+    kn = np.linalg.norm(k)
+    phase = sum(k[d] * coords[d] for d in range(dim)) - kn * cs * t
+    w = amp * np.sin(phase)
+    v = np.stack([w * k[d] / kn for d in range(dim)])
+    P = P0 + rho0 * h0 * cs * w
+    rho = rho0 + rho0 * w / cs
+    return rho, v, P
+
+
+def sound_period(cfg: dict) -> float:
+    """Time for the sound wave of sound_primitives to travel one wavelength."""
+    gam = cfg["gamma_ad"]
+    h0 = 1.0 + gam / (gam - 1.0)
+    cs = np.sqrt(gam / h0)
+    return 1.0 / (np.sqrt(cfg["dim"]) * cs)
+
+
 def kh_perturbation(cfg: dict, seed: int = 4, sigma: float = 1e-3):
     """Seeded Gaussian per-node perturbation of the initial v_y (sigma = 1e-3 c)."""
     rng = np.random.default_rng(seed)
@@ -229,6 +270,8 @@ def initial_primitives(cfg: dict, seed: int | None = None):
         return random3d_primitives(cfg, seed=5 if seed is None else seed)
     if init == "kh_paper":
         return kh_paper_primitives(cfg)
+    if init == "sound":
+        return sound_primitives(cfg)
     raise ValueError(f"unknown init {init!r}")
 
 
