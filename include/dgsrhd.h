@@ -152,10 +152,12 @@ int dg_ssprk3_step_vjp(dg_ctx* ctx, const double* Un_dev, double dt,
 
 /* Taped step for the adjoint of a trajectory: dg_ssprk3_step in place on U_dev,
  * also recording into tape_dev (dg_tape_size doubles, caller-owned) the
- * primitives of the three stage inputs and the three stage outputs before the
- * physicality operator.  dg_ssprk3_step_vjp_tape then applies the step's
- * vector-Jacobian product from that tape without recomputing the forward step;
- * lam_next_dev and lam_n_dev may alias. */
+ * primitives of the three stage inputs, the three stage outputs before the
+ * physicality operator and, in a trailing block, whether the operator changed
+ * any element in each stage (the reverse then skips the operator's adjoint, an
+ * identity, without a host synchronisation).  dg_ssprk3_step_vjp_tape applies the
+ * step's vector-Jacobian product from that tape without recomputing the forward
+ * step; lam_next_dev and lam_n_dev may alias. */
 size_t dg_tape_size(const dg_ctx* ctx);
 int dg_ssprk3_step_tape(dg_ctx* ctx, double* U_dev, double dt, double* tape_dev);
 int dg_ssprk3_step_vjp_tape(dg_ctx* ctx, const double* tape_dev, double dt, const double* lam_next_dev,

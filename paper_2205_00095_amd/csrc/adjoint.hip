@@ -14,11 +14,27 @@ namespace {
 size_t state_doubles(const dg_ctx* c) { return (size_t)c->nv * (size_t)c->ntot; }
 int obj_blocks(const dg_ctx* c) { return (int)((c->ntot + 255) / 256); }
 
-// Adjoint scratch: Utmp, a 6-state tape, mu_a, mu_b, lamn, then objective partials.
-enum { A_UTMP = 0, A_TAPE = 1, A_MUA = 7, A_MUB = 8, A_LAMN = 9, A_NSTATES = 10 };
+// A tape: W(U^n), W(U1), W(U2), the three pre-operator stage outputs, then a
+// flag block (kTapeFlagDoubles doubles, keeping later tapes 256-byte aligned)
+// whose first three unsigned ints say whether the operator changed an element in
+// stage 1, 2, 3.
+constexpr size_t kTapeFlagDoubles = 32;
+size_t tape_doubles(const dg_ctx* c) { return 6 * state_doubles(c) + kTapeFlagDoubles; }
+unsigned* tape_flags(double* tape, const dg_ctx* c) { return (unsigned*)(tape + 6 * state_doubles(c)); }
+const unsigned* tape_flags(const double* tape, const dg_ctx* c) {
+  return (const unsigned*)(tape + 6 * state_doubles(c));
+}
+
+// Adjoint scratch: Utmp, one tape, mu_a, mu_b, lamn, then objective partials.
+enum { A_UTMP = 0, A_TAPE = 1, A_MUA = 2, A_MUB = 3, A_LAMN = 4 };
+
+size_t adj_offset(const dg_ctx* c, int k) {
+  const size_t S = state_doubles(c);
+  return k == A_UTMP ? 0 : (k == A_TAPE ? S : S + tape_doubles(c) + (size_t)(k - A_MUA) * S);
+}
 
 int ensure_adj(dg_ctx* c) {
-  const size_t need = A_NSTATES * state_doubles(c) + (size_t)obj_blocks(c) + 8;
+  const size_t need = adj_offset(c, A_LAMN) + state_doubles(c) + (size_t)obj_blocks(c) + 8;
   if (c->adj && c->adj_doubles >= need) return DG_OK;
   if (c->adj) {
     int r = hipcheck(c, hipStreamSynchronize(c->stream), "adjoint scratch");
@@ -34,7 +50,25 @@ int ensure_adj(dg_ctx* c) {
   return DG_OK;
 }
 
-double* adj_state(dg_ctx* c, int k) { return c->adj + (size_t)k * state_doubles(c); }
+double* adj_state(dg_ctx* c, int k) { return c->adj + adj_offset(c, k); }
+double* adj_partials(dg_ctx* c) { return c->adj + adj_offset(c, A_LAMN) + state_doubles(c); }
+
+// Clears the operator flags of nsteps consecutive tapes (a kernel, so that a
+// captured sequence holds no memset node).
+__global__ void k_clear_tape_flags(double* tapes, long long tape_stride, long long flag_offset, int nsteps) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nsteps) {
+    unsigned* f = (unsigned*)(tapes + (long long)s * tape_stride + flag_offset);
+    f[0] = f[1] = f[2] = 0u;
+  }
+}
+
+hipError_t clear_tape_flags(dg_ctx* c, double* tapes, int nsteps) {
+  if (nsteps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clear_tape_flags, dim3((nsteps + 255) / 256), dim3(256), 0, c->stream, tapes,
+                     (long long)tape_doubles(c), (long long)(6 * state_doubles(c)), nsteps);
+  return hipGetLastError();
+}
 
 hipError_t L_vjp(dg_ctx* c, int mode, const VjpArgs& a) {
   const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos;
@@ -43,11 +77,11 @@ hipError_t L_vjp(dg_ctx* c, int mode, const VjpArgs& a) {
   return launch_vjp_dim3(p, eos, mode, a, c->stream);
 }
 
-hipError_t L_enforce_vjp(dg_ctx* c, const double* Pst, const double* lin, double* lout) {
+hipError_t L_enforce_vjp(dg_ctx* c, const double* Pst, const double* lin, double* lout, const unsigned* flag) {
   const int dim = c->desc.dim, p = c->desc.p;
-  if (dim == 1) return launch_enforce_vjp_dim1(p, Pst, lin, lout, c->m, c->t, c->q, c->stream);
-  if (dim == 2) return launch_enforce_vjp_dim2(p, Pst, lin, lout, c->m, c->t, c->q, c->stream);
-  return launch_enforce_vjp_dim3(p, Pst, lin, lout, c->m, c->t, c->q, c->stream);
+  if (dim == 1) return launch_enforce_vjp_dim1(p, Pst, lin, lout, flag, c->m, c->t, c->q, c->stream);
+  if (dim == 2) return launch_enforce_vjp_dim2(p, Pst, lin, lout, flag, c->m, c->t, c->q, c->stream);
+  return launch_enforce_vjp_dim3(p, Pst, lin, lout, flag, c->m, c->t, c->q, c->stream);
 }
 
 VjpArgs vjp_args(dg_ctx* c) {
@@ -83,15 +117,19 @@ int step_tape(dg_ctx* c, double* U, double dt, double* tape, const char* what, b
   double* P1 = tape + 3 * S;
   double* P2 = tape + 4 * S;
   double* P3 = tape + 5 * S;
+  unsigned* flags = tape_flags(tape, c);  // cleared by the caller
   int r;
   if (!have_w0 && (r = hipcheck(c, L_con2prim(c, U, W0), what))) return r;
   ElemArgs a = base_args(c);
   a.dt = dt;
   a.W = W0; a.Uk = U; a.Un = U; a.ca = 0.0; a.cb = 1.0; a.out = c->U1; a.Wout = W1; a.Pout = P1;
+  a.opflag = flags;
   if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
   a.W = W1; a.Uk = c->U1; a.ca = 0.75; a.cb = 0.25; a.out = c->U2; a.Wout = W2; a.Pout = P2;
+  a.opflag = flags + 1;
   if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
   a.W = W2; a.Uk = c->U2; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.out = U; a.Wout = next_w0; a.Pout = P3;
+  a.opflag = flags + 2;
   return hipcheck(c, L_element(c, MODE_STAGE, a), what);
 }
 
@@ -108,25 +146,32 @@ int step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_ne
   double* mua = adj_state(c, A_MUA);
   double* mub = adj_state(c, A_MUB);
   double* lamn = adj_state(c, A_LAMN);
+  const unsigned* flags = tape_flags(tape, c);  // operator active in stages 1, 2, 3 of the forward step
   const bool phys = c->desc.phys != 0;
   int r;
-  const double* mu3 = lam_next;
-  if (phys) {
-    if ((r = hipcheck(c, L_enforce_vjp(c, P3, lam_next, mua), what))) return r;
-    mu3 = mua;
-  }
   VjpArgs a = vjp_args(c);
   a.dt = dt;
+  // the operator after stage 3, when it acted: mua = Pi'(P3)^T lam_next (else
+  // nothing is written and stage 3 reads lam_next)
+  a.lam = lam_next;
+  if (phys) {
+    if ((r = hipcheck(c, L_enforce_vjp(c, P3, lam_next, mua, flags + 2), what))) return r;
+    a.lam_alt = mua;
+    a.lam_sel = flags + 2;
+  }
   // stage 3: U^{n+1} = Pi(1/3 U^n + 2/3 (U2 + dt R(U2)))
-  a.W = W2; a.lam = mu3; a.out = mub; a.lamn = lamn; a.lamn_init = 1;
-  a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.Pprev = phys ? P2 : nullptr;
+  a.W = W2; a.out = mub; a.lamn = lamn; a.lamn_init = 1;
+  a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.Pprev = phys ? P2 : nullptr; a.pflag = flags + 1;
   if ((r = hipcheck(c, L_vjp(c, VJP_STAGE, a), what))) return r;
   // stage 2: U2 = Pi(3/4 U^n + 1/4 (U1 + dt R(U1)))
   double* mu1 = mua;  // mu3 (mua or lam_next) is no longer read
+  a.lam_alt = nullptr;
+  a.lam_sel = nullptr;
   a.W = W1; a.lam = mub; a.out = mu1; a.lamn_init = 0; a.ca = 0.75; a.cb = 0.25; a.Pprev = phys ? P1 : nullptr;
+  a.pflag = flags;
   if ((r = hipcheck(c, L_vjp(c, VJP_STAGE, a), what))) return r;
   // stage 1: U1 = Pi(U^n + dt R(U^n))
-  a.W = W0; a.lam = mu1; a.out = lam_n; a.ca = 0.0; a.cb = 1.0; a.Pprev = nullptr;
+  a.W = W0; a.lam = mu1; a.out = lam_n; a.ca = 0.0; a.cb = 1.0; a.Pprev = nullptr; a.pflag = nullptr;
   return hipcheck(c, L_vjp(c, VJP_STAGE, a), what);
 }
 
@@ -148,12 +193,14 @@ int dg_rhs_vjp(dg_ctx* c, const double* U, const double* lamR, double* lamU) {
   return finish(c, "dg_rhs_vjp");
 }
 
-size_t dg_tape_size(const dg_ctx* c) { return c ? 6 * state_doubles(c) : 0; }
+size_t dg_tape_size(const dg_ctx* c) { return c ? tape_doubles(c) : 0; }
 
 int dg_ssprk3_step_tape(dg_ctx* c, double* U, double dt, double* tape) {
   if (!c) return DG_EINVAL;
   if (!U || !tape) return fail(c, DG_EINVAL, "dg_ssprk3_step_tape: null pointer");
-  int r = step_tape(c, U, dt, tape, "dg_ssprk3_step_tape");
+  int r = hipcheck(c, clear_tape_flags(c, tape, 1), "dg_ssprk3_step_tape");
+  if (r) return r;
+  r = step_tape(c, U, dt, tape, "dg_ssprk3_step_tape");
   if (r) return r;
   return finish(c, "dg_ssprk3_step_tape");
 }
@@ -171,7 +218,9 @@ int dg_ssprk3_run_tape(dg_ctx* c, double* U, double dt, int nsteps, double* tape
   if (!c) return DG_EINVAL;
   if (!U || !tapes) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: null pointer");
   if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: nsteps < 0");
-  const size_t T = 6 * state_doubles(c);
+  const size_t T = tape_doubles(c);
+  int r0 = hipcheck(c, clear_tape_flags(c, tapes, nsteps), "dg_ssprk3_run_tape");
+  if (r0) return r0;
   for (int s = 0; s < nsteps; ++s) {
     double* next_w0 = (s + 1 < nsteps) ? tapes + (size_t)(s + 1) * T : nullptr;
     int r = step_tape(c, U, dt, tapes + (size_t)s * T, "dg_ssprk3_run_tape", s > 0, next_w0);
@@ -186,7 +235,7 @@ int dg_ssprk3_run_vjp_tape(dg_ctx* c, const double* tapes, double dt, int nsteps
   if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_vjp_tape: nsteps < 0");
   int r = ensure_adj(c);
   if (r) return r;
-  const size_t T = 6 * state_doubles(c);
+  const size_t T = tape_doubles(c);
   for (int s = nsteps - 1; s >= 0; --s) {
     if ((r = step_vjp_tape(c, tapes + (size_t)s * T, dt, lam, lam, "dg_ssprk3_run_vjp_tape"))) return r;
   }
@@ -203,6 +252,7 @@ int dg_ssprk3_step_vjp(dg_ctx* c, const double* Un, double dt, const double* lam
   r = hipcheck(c, hipMemcpyAsync(Ut, Un, state_doubles(c) * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
                "dg_ssprk3_step_vjp");
   if (r) return r;
+  if ((r = hipcheck(c, clear_tape_flags(c, tape, 1), "dg_ssprk3_step_vjp"))) return r;
   if ((r = step_tape(c, Ut, dt, tape, "dg_ssprk3_step_vjp"))) return r;
   if ((r = step_vjp_tape(c, tape, dt, lam_next, lam_n, "dg_ssprk3_step_vjp"))) return r;
   return finish(c, "dg_ssprk3_step_vjp");
@@ -214,7 +264,7 @@ int dg_objective_vy2(dg_ctx* c, const double* U, double* J_host, double* dJdU) {
   int r = ensure_adj(c);
   if (r) return r;
   const int nb = obj_blocks(c);
-  double* partial = c->adj + A_NSTATES * state_doubles(c);
+  double* partial = adj_partials(c);
   double* Jdev = partial + nb;
   double jac = 1.0;
   for (int d = 0; d < c->desc.dim; ++d) jac *= 1.0 / c->m.two_dx[d];  // prod dx_d / 2

@@ -21,6 +21,9 @@ namespace dgsrhd {
 struct VjpArgs {
   const double* W;      // primitives of the linearisation point
   const double* lam;    // adjoint of R (plain) or of the stage's pre-operator output (stage)
+  const double* lam_alt;     // read instead of lam when *lam_sel != 0 (lam_sel may be null)
+  const unsigned* lam_sel;
+  const unsigned* pflag;     // the forward operator of the previous stage changed nothing when *pflag == 0
   double* out;          // lambda_U (plain); previous stage's adjoint or lambda_n (stage)
   double* lamn;         // running adjoint of U^n (stage mode)
   const double* Pprev;  // pre-operator state of the previous stage (stage mode), or null
@@ -169,12 +172,16 @@ __device__ __forceinline__ void physicality_vjp_block(const double* Pn, double* 
   __syncthreads();
 }
 
+// flag, when given, is the forward stage's operator flag: 0 means the operator
+// changed nothing, its adjoint is the identity and nothing is written (the caller
+// then reads lam_in).
 template <int DIM, int P>
 __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce_vjp(const double* __restrict__ Pst,
                                                                    const double* __restrict__ lam_in,
                                                                    double* __restrict__ lam_out, MeshArgs m, Tables t,
-                                                                   PhysParams q) {
+                                                                   PhysParams q, const unsigned* flag) {
   using G = Geo<DIM, P>;
+  if (flag && *flag == 0u) return;
   constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, EPB = G::EPB;
   __shared__ double sbuf[(NV + 1) * NT];
   __shared__ double sred[NV * EPB];
@@ -229,12 +236,13 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, EOS>()))
   const bool act = (o[0] + lc[0] < m.nex) && (o[1] + lc[1] < m.ney) && (o[2] + lc[2] < m.nez);
   const long long e = act ? ((long long)(o[2] + lc[2]) * m.ney + (o[1] + lc[1])) * m.nex + (o[0] + lc[0]) : 0;
   const long long g = e * NPE + node;
+  const double* const lam_in = (a.lam_sel && *a.lam_sel != 0u) ? a.lam_alt : a.lam;
 
   double W[NV], mu[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     W[v] = act ? a.W[v * ntot + g] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
-    mu[v] = act ? a.lam[v * ntot + g] : 0.0;
+    mu[v] = act ? lam_in[v * ntot + g] : 0.0;
     sW[v * NT + tid] = W[v];
     sL[v * NT + tid] = mu[v];
   }
@@ -292,7 +300,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, EOS>()))
         have_L = ge >= 0;
         if (have_L) {
           srcW = a.W + ge * NPE;
-          srcL = a.lam + ge * NPE;
+          srcL = lam_in + ge * NPE;
           stride = ntot;
         }
       }
@@ -331,7 +339,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, EOS>()))
         have_R = ge >= 0;
         if (have_R) {
           srcW = a.W + ge * NPE;
-          srcL = a.lam + ge * NPE;
+          srcL = lam_in + ge * NPE;
           stride = ntot;
         }
       }
@@ -428,11 +436,13 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, EOS>()))
       acc[v] = prev + a.ca * mu[v];
     }
     if (a.Pprev) {
-      double Pn[NV];
+      if (!a.pflag || *a.pflag != 0u) {
+        double Pn[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Pn[v] = act ? a.Pprev[v * ntot + g] : 1.0;
-      __syncthreads();
-      physicality_vjp_block<DIM, P, NT, EPB>(Pn, lp, act, tid, el, node, t, q, sL, sred, sflag);
+        for (int v = 0; v < NV; ++v) Pn[v] = act ? a.Pprev[v * ntot + g] : 1.0;
+        __syncthreads();
+        physicality_vjp_block<DIM, P, NT, EPB>(Pn, lp, act, tid, el, node, t, q, sL, sred, sflag);
+      }
       if (act) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {

@@ -79,6 +79,7 @@ struct ElemArgs {
   Tables t;
   PhysParams q;
   Counters* cnt;
+  unsigned* opflag;   // set to 1 when the operator changed an element (taped stages), or null
 };
 
 // Wave-aggregated event counting: one atomic per wave and counter (the counters are
@@ -672,6 +673,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     if (a.phys) {
       __syncthreads();
       changed = physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag);
+      if (a.opflag && changed && tid == 0) *a.opflag = 1u;
     }
     if (act) {
 #pragma unroll
