@@ -206,12 +206,13 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce_vjp(const double*
 
 // Waves per SIMD the adjoint element kernel is compiled for: 3 (at most 168 VGPRs,
 // a few spills) measured faster than 2 for the 2D ideal-gas kernels; elsewhere the
-// spills at 3 would be heavy.
-template <int DIM, int EOS>
-constexpr int vjp_min_waves() { return (DIM == 2 && EOS == EOS_IDEAL) ? 3 : 2; }
+// spills at 3 would be heavy.  At p = 0 the tile's LDS already caps the occupancy
+// below either bound, so none is asked for.
+template <int DIM, int P, int EOS>
+constexpr int vjp_min_waves() { return P == 0 ? 1 : (DIM == 2 && EOS == EOS_IDEAL) ? 3 : 2; }
 
 template <int DIM, int P, int EOS, int MODE>
-__global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, EOS>())) void k_rhs_vjp(VjpArgs a) {
+__global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>())) void k_rhs_vjp(VjpArgs a) {
   using T = TileGeo<DIM, P>;
   constexpr int N1 = T::N1, NPE = T::NPE, NV = T::NV, NT = T::NT, EPB = T::EPB;
   constexpr int NFP = T::NFP, FPB = T::FPB, TX = T::TX, TY = T::TY;

@@ -362,26 +362,89 @@ __device__ __forceinline__ X sel3(int d, X a, X b, X c) { return d == 0 ? a : (d
 template <int DIM, int P>
 struct TileFacePoint {
   int d, f, pt;
+  int fidx;                 // index in the tile's face-point list (tile_face_index)
   int loc0, lstride;        // tile-local element of the face's row at coordinate 0 along d; stride along d
   long long gbase, gstride; // the same in global element numbering
   int od, nnd, per;         // tile origin, mesh extent and periodicity along d
   bool left_local, right_local;
 
+  // point fp of the face-point list (tile_face_index order)
   __device__ __forceinline__ TileFacePoint(int fp, const int* o, const MeshArgs& m) {
     using T = TileGeo<DIM, P>;
-    int fi, l0, l1, l2;
-    if (fp < T::FOFF1) { d = 0; fi = fp; }
-    else if (DIM > 1 && fp < T::FOFF2) { d = 1; fi = fp - T::FOFF1; }
-    else { d = 2; fi = fp - T::FOFF2; }
+    int dd, fi, l0, l1, l2, ff;
+    if (fp < T::FOFF1) { dd = 0; fi = fp; }
+    else if (DIM > 1 && fp < T::FOFF2) { dd = 1; fi = fp - T::FOFF1; }
+    else { dd = 2; fi = fp - T::FOFF2; }
     const int face = fi / T::NFP;
-    pt = fi - face * T::NFP;
-    if (d == 0) {
-      f = face % (T::TX + 1); l1 = (face / (T::TX + 1)) % T::TY; l2 = face / ((T::TX + 1) * T::TY); l0 = 0;
-    } else if (d == 1) {
-      l0 = face % T::TX; f = (face / T::TX) % (T::TY + 1); l2 = face / (T::TX * (T::TY + 1)); l1 = 0;
+    const int p = fi - face * T::NFP;
+    if (dd == 0) {
+      ff = face % (T::TX + 1); l1 = (face / (T::TX + 1)) % T::TY; l2 = face / ((T::TX + 1) * T::TY); l0 = 0;
+    } else if (dd == 1) {
+      l0 = face % T::TX; ff = (face / T::TX) % (T::TY + 1); l2 = face / (T::TX * (T::TY + 1)); l1 = 0;
     } else {
-      l0 = face % T::TX; l1 = (face / T::TX) % T::TY; f = face / (T::TX * T::TY); l2 = 0;
+      l0 = face % T::TX; l1 = (face / T::TX) % T::TY; ff = face / (T::TX * T::TY); l2 = 0;
     }
+    init(dd, ff, l0, l1, l2, p, o, m);
+    fidx = fp;
+  }
+
+  // Point taken by slot k of the face phase.  Slots run over the points of the tile's
+  // own boundary faces first (f = 0 or f = T_d: one side belongs to a neighbouring
+  // tile and is read from HBM), then over the inner ones (both sides in LDS), so a
+  // wave meets (nearly) one kind of point and runs one load path per side.
+  __device__ __forceinline__ static TileFacePoint from_slot(int k, const int* o, const MeshArgs& m) {
+    using T = TileGeo<DIM, P>;
+    constexpr int NFP = T::NFP, TX = T::TX, TY = T::TY, TZ = T::TZ;
+    constexpr int C0 = TY * TZ, C1 = TX * TZ, C2 = TX * TY;  // faces per tile layer normal to x, y, z
+    constexpr int B0 = 2 * C0 * NFP, B1 = DIM > 1 ? 2 * C1 * NFP : 0, B2 = DIM > 2 ? 2 * C2 * NFP : 0;
+    constexpr int NB = B0 + B1 + B2;  // boundary points
+    constexpr int I0 = (TX - 1) * C0 * NFP, I1 = DIM > 1 ? (TY - 1) * C1 * NFP : 0;
+    constexpr int I2 = DIM > 2 ? (TZ - 1) * C2 * NFP : 0;
+    static_assert(NB + I0 + I1 + I2 == T::FPB, "every face point has one slot");
+    constexpr int N0 = TX > 1 ? TX - 1 : 1, N1 = TY > 1 ? TY - 1 : 1, N2 = TZ > 1 ? TZ - 1 : 1;
+    int dd, r, ff, cross;
+    if (k < NB) {
+      if (DIM == 1 || k < B0) { dd = 0; r = k; }
+      else if (DIM == 2 || k < B0 + B1) { dd = 1; r = k - B0; }
+      else { dd = 2; r = k - B0 - B1; }
+      const int p = r % NFP;
+      r /= NFP;
+      const int cd = sel3(dd, C0, C1, C2);
+      const bool hi = r >= cd;
+      cross = hi ? r - cd : r;
+      ff = hi ? sel3(dd, TX, TY, TZ) : 0;
+      r = p;
+    } else {
+      r = k - NB;
+      if (DIM == 1 || r < I0) { dd = 0; }
+      else if (DIM == 2 || r < I0 + I1) { dd = 1; r -= I0; }
+      else { dd = 2; r -= I0 + I1; }
+      const int p = r % NFP;
+      r /= NFP;
+      // r = cross (T_d - 1) + f - 1
+      cross = sel3(dd, r / N0, r / N1, r / N2);
+      ff = 1 + r - cross * sel3(dd, N0, N1, N2);
+      r = p;
+    }
+    // coordinates of the face's cross-section (the one along d is 0)
+    const int l0 = dd == 0 ? 0 : cross % TX;
+    const int l1 = dd == 0 ? cross % TY : (dd == 1 ? 0 : cross / TX);
+    const int l2 = dd == 0 ? cross / TY : (dd == 1 ? cross / TX : 0);
+    TileFacePoint fc;
+    fc.init(dd, ff, l0, l1, l2, r, o, m);
+    const int l[3] = {l0, l1, l2};
+    fc.fidx = tile_face_index<DIM, P>(dd, ff, l, r);
+    return fc;
+  }
+
+  __device__ __forceinline__ TileFacePoint() {}
+
+  __device__ __forceinline__ void init(int dd, int ff, int l0, int l1, int l2, int p, const int* o,
+                                       const MeshArgs& m) {
+    using T = TileGeo<DIM, P>;
+    d = dd;
+    f = ff;
+    pt = p;
     // the coordinate along d is 0 here and every tile origin lies inside the mesh
     const bool inside = (o[0] + l0 < m.nex) && (o[1] + l1 < m.ney) && (o[2] + l2 < m.nez);
     od = sel3(d, o[0], o[1], o[2]);
@@ -425,6 +488,50 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb >> 3, r = nb & 7;
   const int x = b & 7, k = b >> 3;
   return x * q + min(x, r) + k;
+}
+
+// Primitive trace at one point of an element face normal to d, interpolated along the
+// element's line of nodes through that point (Sec. 2.4 traces, reading R12 for the
+// fallback).  The weights are l_b(+1) taken over the nodes n0, n0 + step, ...,
+// n0 + P step: on the element's + face n0 is the line's first node and step its
+// stride, on its - face n0 is the last node and step the negated stride, since
+// l_b(-1) = l_{P-b}(+1) on the symmetric Gauss-Legendre nodes.  When rho or P
+// interpolates to <= 0 the primitives of the node nearest the face
+// (n0 + P step) are used instead; returns whether that happened.
+template <int NV, int NT, int P>
+__device__ __forceinline__ bool trace_lds(const double* sW, int n0, int step, const Tables& t, double* Wt) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) acc += t.lp[b] * sW[v * NT + n0 + b * step];
+    Wt[v] = acc;
+  }
+  if (!(Wt[0] > 0.0) || !(Wt[NV - 1] > 0.0)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wt[v] = sW[v * NT + n0 + P * step];
+    return true;
+  }
+  return false;
+}
+
+// The same from the state in HBM: src points at node n0 of component 0.
+template <int NV, int P>
+__device__ __forceinline__ bool trace_glb(const double* src, long long ntot, int step, const Tables& t,
+                                          double* Wt) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) acc += t.lp[b] * src[v * ntot + b * step];
+    Wt[v] = acc;
+  }
+  if (!(Wt[0] > 0.0) || !(Wt[NV - 1] > 0.0)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wt[v] = src[v * ntot + P * step];
+    return true;
+  }
+  return false;
 }
 
 // Materialise a value in registers at this point of the program: its computation
@@ -522,101 +629,46 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   }
   __syncthreads();
 
-  // ---- faces of the tile: primitive traces (FP64), exterior states, HLL flux per face point
+  // ---- faces of the tile: primitive traces (FP64), exterior states, HLL flux per face point.
+  // Side A of a face point is an element in this tile (the left one when it is), side B
+  // the other one: in this tile (LDS), in a neighbouring tile (HBM), or absent at an
+  // outflow boundary, where the exterior state equals the interior trace.
   unsigned nfb = 0;  // trace fallbacks seen by this lane
-  for (int fp = tid; fp < FPB; fp += NT) {
-    const TileFacePoint<DIM, P> fc(fp, o, m);
+  for (int k = tid; k < FPB; k += NT) {
+    const TileFacePoint<DIM, P> fc = TileFacePoint<DIM, P>::from_slot(k, o, m);
     if (!fc.left_local && !fc.right_local) continue;
-    const int d = fc.d, pt = fc.pt;
+    const int d = fc.d;
+    const int line0 = line_node<DIM, N1>(d, fc.pt, 0);
+    const int stride = sel3(d, 1, N1, N1 * N1);
+    const bool a_left = fc.left_local;
+    // + face of the left element: forward along the line; - face of the right: backward
+    const int fwd0 = line0, bwd0 = line0 + P * stride;
+    double WA[NV], WB[NV];
+    {
+      const int ob = (a_left ? fc.left_elem() : fc.right_elem()) * NPE;
+      nfb += trace_lds<NV, NT, P>(sW, ob + (a_left ? fwd0 : bwd0), a_left ? stride : -stride, t, WA);
+    }
+    if (a_left && fc.right_local) {
+      nfb += trace_lds<NV, NT, P>(sW, fc.right_elem() * NPE + bwd0, -stride, t, WB);
+    } else {
+      const long long ge = a_left ? fc.right_global() : fc.left_global();
+      if (ge >= 0) {
+        nfb += trace_glb<NV, P>(a.W + ge * NPE + (a_left ? bwd0 : fwd0), ntot, a_left ? -stride : stride, t, WB);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) WB[v] = WA[v];
+      }
+    }
     double WL[NV], WR[NV];
-    bool have_L = true, have_R = true;
-    // left state: + trace of the left element
-    if (fc.left_local) {
-      const int ob = fc.left_elem() * NPE;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double acc = 0.0;
-#pragma unroll
-        for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
-        WL[v] = acc;
-      }
-      if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
-        const int nb = ob + line_node<DIM, N1>(d, pt, P);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) WL[v] = sW[v * NT + nb];
-        nfb++;
-      }
-    } else {
-      const long long ge = fc.left_global();
-      have_L = ge >= 0;
-      if (have_L) {
-        const long long nbase = ge * NPE;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const double* src = a.W + v * ntot + nbase;
-          double acc = 0.0;
-#pragma unroll
-          for (int aa = 0; aa < N1; ++aa) acc += t.lp[aa] * src[line_node<DIM, N1>(d, pt, aa)];
-          WL[v] = acc;
-        }
-        if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
-          const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, P);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) WL[v] = src[v * ntot];
-          nfb++;
-        }
-      }
-    }
-    // right state: - trace of the right element
-    if (fc.right_local) {
-      const int ob = fc.right_elem() * NPE;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double acc = 0.0;
-#pragma unroll
-        for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * sW[v * NT + ob + line_node<DIM, N1>(d, pt, aa)];
-        WR[v] = acc;
-      }
-      if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
-        const int nb = ob + line_node<DIM, N1>(d, pt, 0);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) WR[v] = sW[v * NT + nb];
-        nfb++;
-      }
-    } else {
-      const long long ge = fc.right_global();
-      have_R = ge >= 0;
-      if (have_R) {
-        const long long nbase = ge * NPE;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const double* src = a.W + v * ntot + nbase;
-          double acc = 0.0;
-#pragma unroll
-          for (int aa = 0; aa < N1; ++aa) acc += t.lm[aa] * src[line_node<DIM, N1>(d, pt, aa)];
-          WR[v] = acc;
-        }
-        if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
-          const double* src = a.W + nbase + line_node<DIM, N1>(d, pt, 0);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) WR[v] = src[v * ntot];
-          nfb++;
-        }
-      }
-    }
-    // outflow boundary: the exterior state equals the interior trace
-    if (!have_L) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) WL[v] = WR[v];
-    }
-    if (!have_R) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) WR[v] = WL[v];
+    for (int v = 0; v < NV; ++v) {
+      WL[v] = a_left ? WA[v] : WB[v];
+      WR[v] = a_left ? WB[v] : WA[v];
     }
     double Fh[NV];
     hll_flux<EOS, DIM>(WL, WR, d, q, Fh);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sFh[v * FPB + fp] = Fh[v];
+    for (int v = 0; v < NV; ++v) sFh[v * FPB + fc.fidx] = Fh[v];
   }
   if (__syncthreads_or(nfb != 0)) {  // block-uniform; all lanes active here
     unsigned long long w = nfb;
