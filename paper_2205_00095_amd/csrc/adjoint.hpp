@@ -204,6 +204,55 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce_vjp(const double*
   }
 }
 
+// Trace of the primitives at one face point (as trace_lds / trace_glb of the forward
+// kernel: weights l_b(+1) over nodes n0 + b step, the nearest node on fallback) and the
+// lift transpose's sum over the same line, sum_b (1/w_b) l_b(+1) lambda(n0 + b step),
+// whose weights the reversal maps the same way (w_{P-b} = w_b).  Returns whether the
+// trace fell back.
+template <int NV, int NT, int P>
+__device__ __forceinline__ bool trace_lam_lds(const double* sW, const double* sL, int n0, int step,
+                                              const Tables& t, double* Wt, double* lt) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double acc = 0.0, lacc = 0.0;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      acc += t.lp[b] * sW[v * NT + n0 + b * step];
+      lacc += t.iw[b] * t.lp[b] * sL[v * NT + n0 + b * step];
+    }
+    Wt[v] = acc;
+    lt[v] = lacc;
+  }
+  if (!(Wt[0] > 0.0) || !(Wt[NV - 1] > 0.0)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wt[v] = sW[v * NT + n0 + P * step];
+    return true;
+  }
+  return false;
+}
+
+template <int NV, int P>
+__device__ __forceinline__ bool trace_lam_glb(const double* srcW, const double* srcL, long long ntot, int step,
+                                              const Tables& t, double* Wt, double* lt) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double acc = 0.0, lacc = 0.0;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+      acc += t.lp[b] * srcW[v * ntot + b * step];
+      lacc += t.iw[b] * t.lp[b] * srcL[v * ntot + b * step];
+    }
+    Wt[v] = acc;
+    lt[v] = lacc;
+  }
+  if (!(Wt[0] > 0.0) || !(Wt[NV - 1] > 0.0)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wt[v] = srcW[v * ntot + P * step];
+    return true;
+  }
+  return false;
+}
+
 // Waves per SIMD the adjoint element kernel is compiled for: 3 (at most 168 VGPRs,
 // a few spills) measured faster than 2 for the 2D ideal-gas kernels; elsewhere the
 // spills at 3 would be heavy.  At p = 0 the tile's LDS already caps the occupancy
@@ -275,113 +324,72 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
   for (int v = 0; v < NV; ++v) pin_reg(lamW[v]);
 
   // ---- faces of the tile: adjoint of each face flux from the lift transposes of both
-  //      adjacent elements, HLL linearised once and reversed for every side in the tile
-  for (int fp = tid; fp < FPB; fp += NT) {
-    const TileFacePoint<DIM, P> fc(fp, o, m);
+  //      adjacent elements, HLL linearised once and reversed for every side in the tile.
+  //      Side A of a face point is an element in this tile (the left one when it is),
+  //      side B the other one (LDS, HBM, or absent at an outflow boundary); the slot
+  //      order puts the tile's boundary face points first (see TileFacePoint).
+  for (int k = tid; k < FPB; k += NT) {
+    const TileFacePoint<DIM, P> fc = TileFacePoint<DIM, P>::from_slot(k, o, m);
     const bool left_local = fc.left_local, right_local = fc.right_local;
     if (!left_local && !right_local) continue;
-    const int d = fc.d, pt = fc.pt;
+    const int d = fc.d;
     const double tdx = sel3(d, m.two_dx[0], m.two_dx[1], m.two_dx[2]);
-    double WL[NV], WR[NV], lamFh[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) lamFh[v] = 0.0;
-    bool have_L = true, have_R = true;
-    int fb = 0;
-    // left element: its + trace; its lift gives -(2/dx) sum_i iw_i lp_i lam_i
-    {
-      const double* srcW = nullptr;
-      const double* srcL = nullptr;
-      long long stride = NT;
-      if (left_local) {
-        const int ob = fc.left_elem() * NPE;
-        srcW = sW + ob;
-        srcL = sL + ob;
-      } else {
-        const long long ge = fc.left_global();
-        have_L = ge >= 0;
-        if (have_L) {
-          srcW = a.W + ge * NPE;
-          srcL = lam_in + ge * NPE;
-          stride = ntot;
-        }
-      }
-      if (have_L) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double acc = 0.0, lacc = 0.0;
-#pragma unroll
-          for (int i = 0; i < N1; ++i) {
-            const int ln_i = line_node<DIM, N1>(d, pt, i);
-            acc += t.lp[i] * srcW[v * stride + ln_i];
-            lacc += t.iw[i] * t.lp[i] * srcL[v * stride + ln_i];
-          }
-          WL[v] = acc;
-          lamFh[v] -= tdx * lacc;
-        }
-        if (!(WL[0] > 0.0) || !(WL[NV - 1] > 0.0)) {
-          fb |= 1;
-          const int nb = line_node<DIM, N1>(d, pt, P);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) WL[v] = srcW[v * stride + nb];
-        }
+    const int line0 = line_node<DIM, N1>(d, fc.pt, 0);
+    const int stride = sel3(d, 1, N1, N1 * N1);
+    const bool a_left = left_local;
+    const int fwd0 = line0, bwd0 = line0 + P * stride;
+    // traces and lift-transpose sums sum_b iw_b lp_b lam_(node b) of both sides
+    double WA[NV], WB[NV], lA[NV], lB[NV];
+    const bool fbA = trace_lam_lds<NV, NT, P>(sW, sL, (a_left ? fc.left_elem() : fc.right_elem()) * NPE +
+                                              (a_left ? fwd0 : bwd0), a_left ? stride : -stride, t, WA, lA);
+    bool fbB = false, have_B = true;
+    if (a_left && right_local) {
+      fbB = trace_lam_lds<NV, NT, P>(sW, sL, fc.right_elem() * NPE + bwd0, -stride, t, WB, lB);
+    } else {
+      const long long ge = a_left ? fc.right_global() : fc.left_global();
+      have_B = ge >= 0;
+      if (have_B) {
+        const long long off = ge * NPE + (a_left ? bwd0 : fwd0);
+        fbB = trace_lam_glb<NV, P>(a.W + off, lam_in + off, ntot, a_left ? -stride : stride, t, WB, lB);
       }
     }
-    // right element: its - trace; its lift gives +(2/dx) sum_i iw_i lm_i lam_i
-    {
-      const double* srcW = nullptr;
-      const double* srcL = nullptr;
-      long long stride = NT;
-      if (right_local) {
-        const int ob = fc.right_elem() * NPE;
-        srcW = sW + ob;
-        srcL = sL + ob;
-      } else {
-        const long long ge = fc.right_global();
-        have_R = ge >= 0;
-        if (have_R) {
-          srcW = a.W + ge * NPE;
-          srcL = lam_in + ge * NPE;
-          stride = ntot;
-        }
-      }
-      if (have_R) {
+    // the left element's lift contributes -(2/dx) sum, the right one's +(2/dx) sum
+    double lamFh[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double acc = 0.0, lacc = 0.0;
-#pragma unroll
-          for (int i = 0; i < N1; ++i) {
-            const int ln_i = line_node<DIM, N1>(d, pt, i);
-            acc += t.lm[i] * srcW[v * stride + ln_i];
-            lacc += t.iw[i] * t.lm[i] * srcL[v * stride + ln_i];
-          }
-          WR[v] = acc;
-          lamFh[v] += tdx * lacc;
-        }
-        if (!(WR[0] > 0.0) || !(WR[NV - 1] > 0.0)) {
-          fb |= 2;
-          const int nb = line_node<DIM, N1>(d, pt, 0);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) WR[v] = srcW[v * stride + nb];
-        }
-      }
+    for (int v = 0; v < NV; ++v) {
+      const double lb = have_B ? lB[v] : 0.0;
+      lamFh[v] = tdx * (a_left ? lb - lA[v] : lA[v] - lb);
     }
     double lamWL[NV], lamWR[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) lamWL[v] = lamWR[v] = 0.0;
-    if (!have_L) {
-      // outflow: exterior = the right trace, both HLL arguments are that trace
-      hll_flux_rev<EOS, DIM>(WR, WR, d, q, lamFh, lamWR, lamWR, true, true);
-    } else if (!have_R) {
-      hll_flux_rev<EOS, DIM>(WL, WL, d, q, lamFh, lamWL, lamWL, true, true);
+    if (!have_B) {
+      // outflow: both HLL arguments are side A's trace
+      double lamWA[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lamWA[v] = 0.0;
+      hll_flux_rev<EOS, DIM>(WA, WA, d, q, lamFh, lamWA, lamWA, true, true);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        lamWL[v] = a_left ? lamWA[v] : 0.0;
+        lamWR[v] = a_left ? 0.0 : lamWA[v];
+      }
     } else {
+      double WL[NV], WR[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        WL[v] = a_left ? WA[v] : WB[v];
+        WR[v] = a_left ? WB[v] : WA[v];
+      }
       hll_flux_rev<EOS, DIM>(WL, WR, d, q, lamFh, lamWL, lamWR, left_local, right_local);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      sLWL[v * FPB + fp] = lamWL[v];
-      sLWR[v * FPB + fp] = lamWR[v];
+      sLWL[v * FPB + fc.fidx] = lamWL[v];
+      sLWR[v * FPB + fc.fidx] = lamWR[v];
     }
-    sfb[fp] = fb;
+    const bool fbL = a_left ? fbA : fbB, fbR = a_left ? fbB : fbA;
+    sfb[fc.fidx] = (fbL ? 1 : 0) | (fbR ? 2 : 0);
   }
   __syncthreads();
 
