@@ -77,16 +77,17 @@ __host__ __device__ __forceinline__ void nodal_flux_rev(const double* W, const P
 // the node's pre-operator state; lam holds the adjoint of the operator output on
 // entry and of its input on exit.  Linearised on the active branch: the
 // element's argmin node, its stage-1/stage-2 case and the average.  sbuf needs
-// (NV + 1) * NT doubles, sred NV * EPB doubles, sflag NT ints.  All threads of
+// (NV + 1) * NT doubles, sred NV * EPB doubles, sflag NT ints, svote one int per
+// wave (for this call only).  All threads of
 // the block must reach it.
 template <int DIM, int P, int NT, int EPB>
 __device__ __forceinline__ void physicality_vjp_block(const double* Pn, double* lam, bool act, int tid, int el,
                                                       int node, const Tables& t, const PhysParams& q, double* sbuf,
-                                                      double* sred, int* sflag) {
+                                                      double* sred, int* sflag, int* svote) {
   using G = Geo<DIM, P>;
   constexpr int NV = G::NV, NPE = G::NPE, N1 = G::N1;
   const bool bad = act && !admissible<DIM>(Pn, q);
-  if (!__syncthreads_or(bad)) return;
+  if (!block_any<(NT + 63) / 64>(bad, svote)) return;
   double wn = t.w[node_coord<N1>(node, 0)];
   if (DIM > 1) wn *= t.w[node_coord<N1>(node, 1)];
   if (DIM > 2) wn *= t.w[node_coord<N1>(node, 2)];
@@ -186,6 +187,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce_vjp(const double*
   __shared__ double sbuf[(NV + 1) * NT];
   __shared__ double sred[NV * EPB];
   __shared__ int sflag[NT];
+  __shared__ int svote[(NT + 63) / 64];
   const int tid = threadIdx.x;
   const int el = tid / NPE, node = tid % NPE;
   const long long e = (long long)blockIdx.x * EPB + el;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce_vjp(const double*
     Pn[v] = act ? Pst[v * m.ntot + g] : 1.0;
     lam[v] = act ? lam_in[v * m.ntot + g] : 0.0;
   }
-  physicality_vjp_block<DIM, P, NT, EPB>(Pn, lam, act, tid, el, node, t, q, sbuf, sred, sflag);
+  physicality_vjp_block<DIM, P, NT, EPB>(Pn, lam, act, tid, el, node, t, q, sbuf, sred, sflag, svote);
   if (act) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) lam_out[v * m.ntot + g] = lam[v];
@@ -272,6 +274,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
   __shared__ int sfb[FPB];           // bit 0: left trace fell back, bit 1: right trace fell back
   __shared__ double sred[(MODE == VJP_STAGE) ? NV * EPB : 1];
   __shared__ int sflag[(MODE == VJP_STAGE) ? NT : 1];
+  __shared__ int svote[(NT + 63) / 64];
 
   const MeshArgs& m = a.m;
   const Tables& t = a.t;
@@ -450,7 +453,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
 #pragma unroll
         for (int v = 0; v < NV; ++v) Pn[v] = act ? a.Pprev[v * ntot + g] : 1.0;
         __syncthreads();
-        physicality_vjp_block<DIM, P, NT, EPB>(Pn, lp, act, tid, el, node, t, q, sL, sred, sflag);
+        physicality_vjp_block<DIM, P, NT, EPB>(Pn, lp, act, tid, el, node, t, q, sL, sred, sflag, svote);
       }
       if (act) {
 #pragma unroll

@@ -91,6 +91,44 @@ __device__ __forceinline__ void count_wave(unsigned long long* ctr, bool flag) {
   if ((int)(threadIdx.x & 63) == leader) atomicAdd(ctr, (unsigned long long)__popcll(m));
 }
 
+// Block-wide OR of a predicate with one barrier: lane 0 of each wave stores its wave's
+// vote in svote[wave], then every lane reads all NW of them.  Each call site needs an
+// svote array of its own (a later vote on the same array could overwrite votes that
+// slower waves are still reading).  All threads of the block must reach it.
+template <int NW>
+__device__ __forceinline__ bool block_any(bool pred, int* svote) {
+  const bool w = __ballot(pred) != 0ull;
+  if ((threadIdx.x & 63) == 0) svote[threadIdx.x >> 6] = w ? 1 : 0;
+  __syncthreads();
+  int r = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) r |= svote[i];
+  return r != 0;
+}
+
+// Ordering of LDS data exchanged only among the nodes of one element.  When NPE divides
+// 64 an element's nodes never straddle two waves, and a wave's LDS accesses are
+// executed in program order, so it is enough that the compiler keeps that order (a
+// wave-scope fence); otherwise a workgroup barrier.
+template <int NPE>
+__device__ __forceinline__ void element_sync() {
+  if constexpr (64 % NPE == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Sum over the wave's active lanes of a per-lane count below 16 (bitwise ballots).
+__device__ __forceinline__ unsigned long long wave_sum16(unsigned x) {
+  unsigned long long s = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) s += (unsigned long long)__popcll(__ballot((x >> b) & 1u)) << b;
+  return s;
+}
+
 // Recovery status: counts failures / non-convergence and records an element index
 // with a failure (the first failing lane of each wave offers its element to an
 // atomic minimum).
@@ -240,15 +278,17 @@ __device__ __forceinline__ double node_factor(const double* Ui, const double* Ub
 
 // Apply the operator to the elements of one workgroup.  Every thread holds one
 // node's U in registers (act = it belongs to a real element); sbuf must hold
-// NV * NT doubles and sflag NT ints.  Must be reached by all threads of the block.
+// NV * NT doubles, sflag NT ints and svote one int per wave (for this call only).
+// Must be reached by all threads of the block; returns false, after one barrier,
+// when no node of the block is flagged.
 template <int DIM, int P, int NTB>
 __device__ __forceinline__ bool physicality_block_t(double* Un, bool act, int tid, int el, int node,
                                                   const Tables& t, const PhysParams& q, Counters* cnt,
-                                                  double* sbuf, int* sflag) {
+                                                  double* sbuf, int* sflag, int* svote) {
   using G = Geo<DIM, P>;
   constexpr int NV = G::NV, NPE = G::NPE, NT = NTB, N1 = G::N1;
   const bool bad = act && !admissible<DIM>(Un, q);
-  if (!__syncthreads_or(bad)) return false;
+  if (!block_any<(NT + 63) / 64>(bad, svote)) return false;
   double wn = t.w[node_coord<N1>(node, 0)];
   if (DIM > 1) wn *= t.w[node_coord<N1>(node, 1)];
   if (DIM > 2) wn *= t.w[node_coord<N1>(node, 2)];
@@ -295,6 +335,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
   constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, EPB = G::EPB;
   __shared__ double sbuf[NV * NT];
   __shared__ int sflag[NT];
+  __shared__ int svote[(NT + 63) / 64];
   const int tid = threadIdx.x;
   const int el = tid / NPE, node = tid % NPE;
   const long long e = (long long)blockIdx.x * EPB + el;
@@ -303,7 +344,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
   double u[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = act ? U[v * m.ntot + g] : 1.0;
-  physicality_block_t<DIM, P, NT>(u, act, tid, el, node, t, q, counter_slot(cnt), sbuf, sflag);
+  physicality_block_t<DIM, P, NT>(u, act, tid, el, node, t, q, counter_slot(cnt), sbuf, sflag, svote);
   if (act) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) U[v * m.ntot + g] = u[v];
@@ -556,6 +597,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   __shared__ double sFh[NV * FPB];
   __shared__ double sFref[(PREC == PREC_FP32) ? DIM * NV * EPB * NFP : 1];
   __shared__ int sflag[(MODE == MODE_STAGE) ? NT : 1];
+  __shared__ int svote[(NT + 63) / 64];
 
   const MeshArgs& m = a.m;
   const Tables& t = a.t;
@@ -591,10 +633,10 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   for (int d = 0; d < DIM; ++d) {
     double F[NV];
     flux_dir<EOS, DIM>(W, sv, d, F);
-    __syncthreads();
+    element_sync<NPE>();  // the previous direction's reads of sF are done
 #pragma unroll
     for (int v = 0; v < NV; ++v) sF[v * NT + tid] = F[v];
-    __syncthreads();
+    element_sync<NPE>();
     const int id = node_coord<N1>(node, d);
     const int pt = face_pt<DIM, N1>(node, d);
     if constexpr (PREC == PREC_FP64) {
@@ -670,12 +712,13 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
 #pragma unroll
     for (int v = 0; v < NV; ++v) sFh[v * FPB + fc.fidx] = Fh[v];
   }
-  if (__syncthreads_or(nfb != 0)) {  // block-uniform; all lanes active here
-    unsigned long long w = nfb;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
-    if ((tid & 63) == 0 && w != 0ull) atomicAdd(&counter_slot(a.cnt)->trace_fallback, w);
+  // trace fallbacks: one atomic per wave that saw any (all lanes are active here)
+  static_assert(2 * ((FPB + NT - 1) / NT) < 16, "per-lane fallback count fits wave_sum16");
+  {
+    const unsigned long long w = wave_sum16(nfb);
+    if (w != 0ull && (tid & 63) == 0) atomicAdd(&counter_slot(a.cnt)->trace_fallback, w);
   }
+  __syncthreads();
 
   // ---- lift: S_i = -sum_d (2/dx_d)(1/w_{i_d}) [l_{i_d}(+1) Fhat^+ - l_{i_d}(-1) Fhat^-]
 #pragma unroll
@@ -723,8 +766,8 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     // admissibility test and the recovery need not repeat it
     bool changed = true;
     if (a.phys) {
-      __syncthreads();
-      changed = physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag);
+      // sF was last read in the volume phase, before the face phase's closing barrier
+      changed = physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag, svote);
       if (a.opflag && changed && tid == 0) *a.opflag = 1u;
     }
     if (act) {
