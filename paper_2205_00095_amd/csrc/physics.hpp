@@ -153,25 +153,31 @@ __host__ __device__ __forceinline__ void flux_dir(const double* W, const StateEv
 
 // Extreme signal speeds along d (Sec. 2.4):
 // lambda_pm = (v_d pm sqrt(sigma (c^2 - v_d^2 + c^2 sigma)))/(1 + sigma),
-// sigma = c_s^2 / (gamma^2 (c^2 - c_s^2)).
+// sigma = c_s^2 / (gamma^2 (c^2 - c_s^2)).  With c_s^2 = c^2 N / M from the EOS
+// (ideal: N = Gamma Theta, M = c^2 + alpha Theta; Taub-Matthews: N = 3 Theta^2 +
+// 5 Theta s, M = 12 Theta^2 + 2 c^4 + 12 Theta s) and K = M - N, multiplying through
+// by gamma^2 K gives the same speeds with one division:
+// lambda_pm = (v_d gamma^2 K pm sqrt(N (gamma^2 K (c^2 - v_d^2) + c^2 N))) / (gamma^2 K + N).
+// K is formed without cancellation: c^2 + (alpha - Gamma) Theta (alpha >= Gamma for
+// Gamma <= 2), resp. 9 Theta^2 + 7 Theta s + 2 c^4.
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void wavespeeds(const double* W, const StateEval<EOS, DIM>& s, int d,
                                                    const PhysParams& q, double& lm, double& lp) {
-  double cs2;
+  double N, K;
   if constexpr (EOS == EOS_IDEAL) {
-    cs2 = q.c2 * q.gam * s.th / (q.c2 + s.he);
+    N = q.gam * s.th;
+    K = q.c2 + (q.alpha - q.gam) * s.th;
   } else {
     const double th = s.th;
-    cs2 = q.c2 * (3.0 * th * th + 5.0 * th * s.sq) / (12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s.sq);
+    N = th * (3.0 * th + 5.0 * s.sq);
+    K = th * (9.0 * th + 7.0 * s.sq) + 2.0 * q.c4;
   }
   const double vd = comp<DIM>(W + 1, d) * s.ig;
-  // with den = gamma^2 (c^2 - c_s^2), sigma = c_s^2/den and
-  // lambda_pm = (vd den pm sqrt(c_s^2 (den (c^2 - vd^2) + c^2 c_s^2))) / (den + c_s^2)
-  const double den = s.g2 * (q.c2 - cs2);
-  const double root = sqrt(cs2 * (den * (q.c2 - vd * vd) + q.c2 * cs2));
-  const double inv = 1.0 / (den + cs2);
-  lm = (vd * den - root) * inv;
-  lp = (vd * den + root) * inv;
+  const double gK = s.g2 * K;
+  const double root = sqrt(N * (gK * (q.c2 - vd * vd) + q.c2 * N));
+  const double inv = 1.0 / (gK + N);
+  lm = (vd * gK - root) * inv;
+  lp = (vd * gK + root) * inv;
 }
 
 // HLL numerical flux along d between left and right primitive states
@@ -328,10 +334,12 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
   }
   int status = C2P_OK;
   double rho = kRhoFloor, P = kPFloor * q.c2, gb = 0.0, Smag = 0.0;
+  double iS = 0.0;  // 1 / |S| (0 at rest)
   if (!ok) {
     status = C2P_INADMISSIBLE;
   } else {
-    Smag = sqrt(s2);
+    iS = s2 > 0.0 ? inv_sqrt(s2) : 0.0;
+    Smag = s2 * iS;
     const double iD = 1.0 / D;
     const double xi = Smag * iD * q.inv_c;
     const double t = tau * iD * q.inv_c2;  // eta - 1
@@ -403,10 +411,11 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
         }
         const double w2 = w * w;
         const double om = (1.0 - w) * (1.0 + w);
-        const double beta = 2.0 * w / (1.0 + w2);
-        rho = D * om / (1.0 + w2);
+        const double r1 = 1.0 / (1.0 + w2);
+        const double beta = 2.0 * w * r1;
+        rho = D * om * r1;
         gb = 2.0 * w / om;
-        P = q.gm1 * (tau - Smag * beta * q.c + D * q.c2 * 2.0 * w2 / (1.0 + w2));
+        P = q.gm1 * (tau - Smag * beta * q.c + D * q.c2 * 2.0 * w2 * r1);
       }
     } else {
       double c1, c2, c3;
@@ -460,12 +469,14 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
         }
       }
       Wc = fmax(Wc, 0.0);
-      const double gam = sqrt(1.0 + Wc);
-      const double beta = sqrt(Wc / (Wc + 1.0));
+      const double g2 = 1.0 + Wc;
+      const double ig = inv_sqrt(g2);  // 1 / gamma
+      const double gam = g2 * ig;
       gb = sqrt(Wc);  // gamma beta
-      rho = D / gam;
+      const double beta = gb * ig;
+      rho = D * ig;
       // P = (X^2 - (rho c^2)^2)/(3X), X = E - M.v, via X_ = X - rho c^2
-      const double Xm = tau - Smag * beta * q.c + D * q.c2 * Wc / (gam * (gam + 1.0));
+      const double Xm = tau - Smag * beta * q.c + D * q.c2 * Wc * ig / (gam + 1.0);
       const double X = Xm + rho * q.c2;
       P = Xm * (Xm + 2.0 * rho * q.c2) / (3.0 * X);
     }
@@ -484,7 +495,7 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
     gb = 0.0;
   }
   W[0] = rho;
-  const double scale = (Smag > 0.0) ? gb * q.c / Smag : 0.0;
+  const double scale = gb * q.c * iS;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) W[1 + j] = scale * U[1 + j];
   W[NV - 1] = P;
