@@ -122,7 +122,14 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
     s.sq = 0.0;
   } else {
     s.sq = sqrt(th * th + (4.0 / 9.0) * q.c4);
-    he = 2.5 * th + 1.5 * th * th / (s.sq + (2.0 / 3.0) * q.c2);
+    // th^2 / (sq + 2/3 c^2) equals sq - 2/3 c^2; the difference costs no division and,
+    // for Theta >= c^2 / 3, loses at most a factor 18 to cancellation (a few 1e-16 of he)
+    const double a = (2.0 / 3.0) * q.c2;
+    if (th >= 0.5 * a) {
+      he = 2.5 * th + 1.5 * (s.sq - a);
+    } else {
+      he = 2.5 * th + 1.5 * th * th / (s.sq + a);
+    }
   }
   const double D = g * rho;
   const double gH = g * rho * (q.c2 + he) * q.inv_c2;  // gamma rho h / c^2
@@ -161,8 +168,8 @@ __host__ __device__ __forceinline__ void flux_dir(const double* W, const StateEv
 // K is formed without cancellation: c^2 + (alpha - Gamma) Theta (alpha >= Gamma for
 // Gamma <= 2), resp. 9 Theta^2 + 7 Theta s + 2 c^4.
 template <int EOS, int DIM>
-__host__ __device__ __forceinline__ void wavespeeds(const double* W, const StateEval<EOS, DIM>& s, int d,
-                                                   const PhysParams& q, double& lm, double& lp) {
+__host__ __device__ __forceinline__ void wavespeeds_nd(const double* W, const StateEval<EOS, DIM>& s, int d,
+                                                      const PhysParams& q, double& nm, double& np, double& den) {
   double N, K;
   if constexpr (EOS == EOS_IDEAL) {
     N = q.gam * s.th;
@@ -175,9 +182,19 @@ __host__ __device__ __forceinline__ void wavespeeds(const double* W, const State
   const double vd = comp<DIM>(W + 1, d) * s.ig;
   const double gK = s.g2 * K;
   const double root = sqrt(N * (gK * (q.c2 - vd * vd) + q.c2 * N));
-  const double inv = 1.0 / (gK + N);
-  lm = (vd * gK - root) * inv;
-  lp = (vd * gK + root) * inv;
+  den = gK + N;  // > 0
+  nm = vd * gK - root;
+  np = vd * gK + root;
+}
+
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void wavespeeds(const double* W, const StateEval<EOS, DIM>& s, int d,
+                                                   const PhysParams& q, double& lm, double& lp) {
+  double nm, np, den;
+  wavespeeds_nd<EOS, DIM>(W, s, d, q, nm, np, den);
+  const double inv = 1.0 / den;
+  lm = nm * inv;
+  lp = np * inv;
 }
 
 // HLL numerical flux along d between left and right primitive states
@@ -192,21 +209,28 @@ __host__ __device__ __forceinline__ void hll_flux(const double* WL, const double
   double FL[NV], FR[NV];
   flux_dir<EOS, DIM>(WL, sL, d, FL);
   flux_dir<EOS, DIM>(WR, sR, d, FR);
-  double lmL, lpL, lmR, lpR;
-  wavespeeds<EOS, DIM>(WL, sL, d, q, lmL, lpL);
-  wavespeeds<EOS, DIM>(WR, sR, d, q, lmR, lpR);
-  const double aL = fmin(lmL, lmR);
-  const double aR = fmax(lpL, lpR);
-  if (aL >= 0.0) {
+  // the speeds as fractions n / den (den > 0), compared and combined without dividing:
+  // lambda_L = nA / dA = min of the lambda_-, lambda_R = nB / dB = max of the lambda_+
+  double nmL, npL, dnL, nmR, npR, dnR;
+  wavespeeds_nd<EOS, DIM>(WL, sL, d, q, nmL, npL, dnL);
+  wavespeeds_nd<EOS, DIM>(WR, sR, d, q, nmR, npR, dnR);
+  const bool lminL = nmL * dnR <= nmR * dnL;
+  const double nA = lminL ? nmL : nmR, dA = lminL ? dnL : dnR;
+  const bool lmaxL = npL * dnR >= npR * dnL;
+  const double nB = lmaxL ? npL : npR, dB = lmaxL ? dnL : dnR;
+  if (nA >= 0.0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) Fh[k] = FL[k];
-  } else if (aR <= 0.0) {
+  } else if (nB <= 0.0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) Fh[k] = FR[k];
   } else {
-    const double inv = 1.0 / (aR - aL);
+    // (l_R F_L - l_L F_R + l_L l_R (U_R - U_L)) / (l_R - l_L), numerator and
+    // denominator multiplied by dA dB
+    const double cL = nB * dA, cR = nA * dB, cU = nA * nB;
+    const double inv = 1.0 / (cL - cR);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) Fh[k] = (aR * FL[k] - aL * FR[k] + aL * aR * (sR.U[k] - sL.U[k])) * inv;
+    for (int k = 0; k < NV; ++k) Fh[k] = (cL * FL[k] - cR * FR[k] + cU * (sR.U[k] - sL.U[k])) * inv;
   }
 }
 
@@ -255,6 +279,21 @@ __host__ __device__ __forceinline__ void tm_cubic_coeffs(double xi, double eta, 
   c1 = 8.0 * ((e2 + x2) * k - 14.0 * x2 * e2) * i16;
   c2 = (k * k - 57.0 * x2 * e2) * i16;
   c3 = -9.0 * x2 * e2 * i16;
+}
+
+// The same cubic multiplied through by 16 D^4 (eta^2 - xi^2)^2 and written in
+// X = D xi = |S| / c, Y = D eta = E / c^2 and D: A W^3 + C1 W^2 + C2 W + C3 with
+// A = 16 (Y^2 - X^2)^2 (no division).  Every coefficient is homogeneous of degree 8
+// in (X, Y, D), so the three may be scaled by one power of two first.
+__host__ __device__ __forceinline__ void tm_cubic_scaled(double X, double Y, double D, double& A, double& C1,
+                                                         double& C2, double& C3) {
+  const double x2 = X * X, e2 = Y * Y;
+  const double dm = (Y - X) * (Y + X);
+  A = 16.0 * dm * dm;
+  const double k = 4.0 * (e2 + x2) - (x2 + D * D);
+  C1 = 8.0 * ((e2 + x2) * k - 14.0 * x2 * e2);
+  C2 = k * k - 57.0 * x2 * e2;
+  C3 = -9.0 * x2 * e2;
 }
 
 // Brent's bracketed root finder (inverse quadratic interpolation / secant with
@@ -340,12 +379,12 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
   } else {
     iS = s2 > 0.0 ? inv_sqrt(s2) : 0.0;
     Smag = s2 * iS;
-    const double iD = 1.0 / D;
-    const double xi = Smag * iD * q.inv_c;
-    const double t = tau * iD * q.inv_c2;  // eta - 1
-    const double eta = 1.0 + t;
     int method = q.c2p;
     if constexpr (EOS == EOS_IDEAL) {
+      const double iD = 1.0 / D;
+      const double xi = Smag * iD * q.inv_c;
+      const double t = tau * iD * q.inv_c2;  // eta - 1
+      const double eta = 1.0 + t;
       const double al = q.alpha;
       double w = 0.0;
       if (method == C2P_QUARTIC) {
@@ -418,39 +457,49 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
         P = q.gm1 * (tau - Smag * beta * q.c + D * q.c2 * 2.0 * w2 * r1);
       }
     } else {
-      double c1, c2, c3;
-      tm_cubic_coeffs(xi, eta, c1, c2, c3);
       double Wc;
-      if (method == C2P_BRENT) {
-        if (c3 == 0.0) {
-          Wc = 0.0;
+      bool done = false;
+      if (method == C2P_NEWTON && Wprev != nullptr) {
+        // Newton on the cubic scaled by 16 D^4 (eta^2 - xi^2)^2 (the same iterates as on
+        // the monic one, without a division for the coefficients), its coefficients from
+        // (X, Y, D) / 2^e with 2^e the binade of D
+        int e;
+        (void)frexp(D, &e);
+        double A, C1, C2, C3;
+        tm_cubic_scaled(ldexp(Smag * q.inv_c, -e), ldexp(tau * q.inv_c2 + D, -e), ldexp(D, -e), A, C1, C2, C3);
+        double u2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) u2 += Wprev[1 + j] * Wprev[1 + j];
+        double Wn = u2 * q.inv_c2;  // gamma^2 - 1 of the previous stage
+        double step = 0.0;
+#pragma unroll
+        for (int it = 0; it < 3; ++it) {
+          const double f = ((A * Wn + C1) * Wn + C2) * Wn + C3;
+          const double fp = (3.0 * A * Wn + 2.0 * C1) * Wn + C2;
+          step = f / fp;
+          Wn -= step;
+        }
+        const double fp = (3.0 * A * Wn + 2.0 * C1) * Wn + C2;
+        if (fabs(step) <= 1e-9 * fabs(Wn) && A > 0.0 && fp > 0.0 && 3.0 * A * Wn + C1 > 0.0) {
+          Wc = Wn;
+          done = true;
+        }
+      }
+      if (!done) {
+        const double iD = 1.0 / D;
+        const double xi = Smag * iD * q.inv_c;
+        const double eta = 1.0 + tau * iD * q.inv_c2;
+        double c1, c2, c3;
+        tm_cubic_coeffs(xi, eta, c1, c2, c3);
+        if (method == C2P_BRENT) {
+          if (c3 == 0.0) {
+            Wc = 0.0;
+          } else {
+            double hi = 200.0 * 200.0 - 1.0;
+            for (int k = 0; k < 60 && (((hi + c1) * hi + c2) * hi + c3) < 0.0; ++k) hi *= 4.0;
+            if (!tm_brent_root(c1, c2, c3, 0.0, hi, Wc)) status = C2P_NOCONV;
+          }
         } else {
-          double hi = 200.0 * 200.0 - 1.0;
-          for (int k = 0; k < 60 && (((hi + c1) * hi + c2) * hi + c3) < 0.0; ++k) hi *= 4.0;
-          if (!tm_brent_root(c1, c2, c3, 0.0, hi, Wc)) status = C2P_NOCONV;
-        }
-      } else {
-        bool done = false;
-        if (method == C2P_NEWTON && Wprev != nullptr) {
-          double u2 = 0.0;
-#pragma unroll
-          for (int j = 0; j < DIM; ++j) u2 += Wprev[1 + j] * Wprev[1 + j];
-          double Wn = u2 * q.inv_c2;  // gamma^2 - 1 of the previous stage
-          double step = 0.0;
-#pragma unroll
-          for (int it = 0; it < 3; ++it) {
-            const double f = ((Wn + c1) * Wn + c2) * Wn + c3;
-            const double fp = (3.0 * Wn + 2.0 * c1) * Wn + c2;
-            step = f / fp;
-            Wn -= step;
-          }
-          const double fp = (3.0 * Wn + 2.0 * c1) * Wn + c2;
-          if (fabs(step) <= 1e-9 * fabs(Wn) && fp > 0.0 && 3.0 * Wn + c1 > 0.0) {
-            Wc = Wn;
-            done = true;
-          }
-        }
-        if (!done) {
           // analytic (trigonometric / Cardano), then one Newton step on the cubic
           const double Q = (3.0 * c2 - c1 * c1) * (1.0 / 9.0);
           const double R = (9.0 * c1 * c2 - 27.0 * c3 - 2.0 * c1 * c1 * c1) * (1.0 / 54.0);
