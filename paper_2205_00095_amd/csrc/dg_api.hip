@@ -353,6 +353,10 @@ int dg_enforce_physical(dg_ctx* c, double* U) {
 // U^(k+1) = Pi(ca U^n + cb (U^(k) + dt L(U^(k)))), one fused launch per stage.
 // order 1: forward Euler; 2: the second-order SSP scheme (1/2, 1/2);
 // 3: the third-order SSP scheme (3/4, 1/4; 1/3, 2/3).
+// The last stage's U^n term is folded into the stage before it: that stage stores
+// Z = ca U^n + cb U^(k) (with the last stage's weights) in place of U^(k), whose
+// primitives it still writes, and the last stage forms Z + cb dt L(U^(k)) reading
+// only Z, one state read fewer per step.
 static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, const char* what) {
   if (!c) return DG_EINVAL;
   if (!U) return fail(c, DG_EINVAL, "%s: null pointer", what);
@@ -361,13 +365,16 @@ static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, c
   if (!std::isfinite(dt)) return fail(c, DG_EINVAL, "%s: dt not finite", what);
   if (nsteps == 0) return DG_OK;
   struct Stage {
-    double ca, cb;
+    double ca, cb, dtf;  // U^(k+1) = ca U^n + cb (U^(k) + dtf dt L)
+    double za, zb;       // stored: za U^n + zb U^(k+1) when za != 0
     double* in;
     double* out;
   };
-  const Stage tab1[1] = {{0.0, 1.0, U, U}};
-  const Stage tab2[2] = {{0.0, 1.0, U, c->U1}, {0.5, 0.5, c->U1, U}};
-  const Stage tab3[3] = {{0.0, 1.0, U, c->U1}, {0.75, 0.25, c->U1, c->U2}, {1.0 / 3.0, 2.0 / 3.0, c->U2, U}};
+  const Stage tab1[1] = {{0.0, 1.0, 1.0, 0.0, 0.0, U, U}};
+  const Stage tab2[2] = {{0.0, 1.0, 1.0, 0.5, 0.5, U, c->U1}, {0.0, 1.0, 0.5, 0.0, 0.0, c->U1, U}};
+  const Stage tab3[3] = {{0.0, 1.0, 1.0, 0.0, 0.0, U, c->U1},
+                         {0.75, 0.25, 1.0, 1.0 / 3.0, 2.0 / 3.0, c->U1, c->U2},
+                         {0.0, 1.0, 2.0 / 3.0, 0.0, 0.0, c->U2, U}};
   const Stage* tab = order == 1 ? tab1 : (order == 2 ? tab2 : tab3);
   double* Wa = c->Wa;
   double* Wb = c->Wb;
@@ -376,12 +383,14 @@ static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, c
   for (int s = 0; s < nsteps; ++s) {
     for (int k = 0; k < order; ++k) {
       ElemArgs a = base_args(c);
-      a.dt = dt;
+      a.dt = dt * tab[k].dtf;
       a.W = Wa;
       a.Uk = tab[k].in;
       a.Un = U;
       a.ca = tab[k].ca;
       a.cb = tab[k].cb;
+      a.za = tab[k].za;
+      a.zb = tab[k].zb;
       a.out = tab[k].out;
       const bool last = (s == nsteps - 1) && (k == order - 1);
       a.Wout = last ? nullptr : Wb;

@@ -73,7 +73,8 @@ struct ElemArgs {
   double* out;        // R (rhs mode) or U^(k+1) (stage mode)
   double* Wout;       // primitives of U^(k+1), or null
   double* Pout;       // U^(k+1) before the physicality operator (adjoint tape), or null
-  double ca, cb, dt;  // U^(k+1) = ca U^n + cb (U^(k) + dt R)
+  double ca, cb, dt;  // U^(k+1) = ca U^n + cb (U^(k) + dt R); U^n is not read when ca = za = 0
+  double za, zb;      // with za != 0 the stored output is za U^n + zb U^(k+1) (after the operator)
   int phys;
   MeshArgs m;
   Tables t;
@@ -751,12 +752,14 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
       for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = R[v];
     }
   } else {
-    double Un[NV];
+    double Un[NV], U0[NV];  // U^(k+1), U^n
+    const bool need_u0 = a.ca != 0.0 || a.za != 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U0[v] = (act && need_u0) ? a.Un[v * ntot + g] : 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double un = act ? a.Un[v * ntot + g] : 1.0;
       const double uk = act ? a.Uk[v * ntot + g] : 1.0;
-      Un[v] = a.ca * un + a.cb * (uk + a.dt * R[v]);
+      Un[v] = a.ca * U0[v] + a.cb * (uk + a.dt * R[v]);
     }
     if (a.Pout && act) {
 #pragma unroll
@@ -771,8 +774,13 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
       if (a.opflag && changed && tid == 0) *a.opflag = 1u;
     }
     if (act) {
+      if (a.za != 0.0) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = Un[v];
+        for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = a.za * U0[v] + a.zb * Un[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = Un[v];
+      }
       if (a.Wout) {
         double Wn[NV];
         double Wp[NV];  // this node's primitives at the start of the stage (Newton start)
