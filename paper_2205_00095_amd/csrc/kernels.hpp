@@ -593,8 +593,12 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   using T = TileGeo<DIM, P>;
   constexpr int N1 = T::N1, NPE = T::NPE, NV = T::NV, NT = T::NT, EPB = T::EPB;
   constexpr int NFP = T::NFP, FPB = T::FPB, TX = T::TX, TY = T::TY, TZ = T::TZ;
-  __shared__ double sW[NV * NT];
-  __shared__ double sF[NV * NT];
+  // sW and sF hold one value per node and variable, elements ES apart: one unused
+  // slot after each element when NPE is even, so that the lanes reading the same
+  // node of neighbouring elements fall in different LDS banks
+  constexpr int ES = NPE % 2 == 0 ? NPE + 1 : NPE, NTP = EPB * ES;
+  __shared__ double sW[NV * NTP];
+  __shared__ double sF[NV * NTP];
   __shared__ double sFh[NV * FPB];
   __shared__ double sFref[(PREC == PREC_FP32) ? DIM * NV * EPB * NFP : 1];
   __shared__ int sflag[(MODE == MODE_STAGE) ? NT : 1];
@@ -618,8 +622,9 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   double W[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) W[v] = act ? a.W[v * ntot + g] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
+  const int ln = el * ES + node;  // this node's slot in sW and sF
 #pragma unroll
-  for (int v = 0; v < NV; ++v) sW[v * NT + tid] = W[v];
+  for (int v = 0; v < NV; ++v) sW[v * NTP + ln] = W[v];
 
   // ---- volume term: V_i = sum_d (2/dx_d) sum_a dhat[i_d][a] F^d(W at node (i with i_d -> a))
   double R[NV];
@@ -636,7 +641,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     flux_dir<EOS, DIM>(W, sv, d, F);
     element_sync<NPE>();  // the previous direction's reads of sF are done
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sF[v * NT + tid] = F[v];
+    for (int v = 0; v < NV; ++v) sF[v * NTP + ln] = F[v];
     element_sync<NPE>();
     const int id = node_coord<N1>(node, d);
     const int pt = face_pt<DIM, N1>(node, d);
@@ -645,19 +650,19 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
       for (int v = 0; v < NV; ++v) {
         double acc = 0.0;
 #pragma unroll
-        for (int aa = 0; aa < N1; ++aa) acc += t.dhat[id][aa] * sF[v * NT + el * NPE + line_node<DIM, N1>(d, pt, aa)];
+        for (int aa = 0; aa < N1; ++aa) acc += t.dhat[id][aa] * sF[v * NTP + el * ES + line_node<DIM, N1>(d, pt, aa)];
         R[v] += m.two_dx[d] * acc;
       }
     } else {
       // deviations from the line's first node, so only the variation along d enters FP32
-      const int n0 = el * NPE + line_node<DIM, N1>(d, pt, 0);
+      const int n0 = el * ES + line_node<DIM, N1>(d, pt, 0);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double ref = sF[v * NT + n0];
+        const double ref = sF[v * NTP + n0];
         float acc = 0.0f;
 #pragma unroll
         for (int aa = 0; aa < N1; ++aa)
-          acc += t.dhat_f[id][aa] * (float)(sF[v * NT + el * NPE + line_node<DIM, N1>(d, pt, aa)] - ref);
+          acc += t.dhat_f[id][aa] * (float)(sF[v * NTP + el * ES + line_node<DIM, N1>(d, pt, aa)] - ref);
         Rf[v] += (float)m.two_dx[d] * acc;
         if (id == 0) sFref[((d * NV + v) * EPB + el) * NFP + pt] = F[v];
       }
@@ -688,11 +693,11 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     const int fwd0 = line0, bwd0 = line0 + P * stride;
     double WA[NV], WB[NV];
     {
-      const int ob = (a_left ? fc.left_elem() : fc.right_elem()) * NPE;
-      nfb += trace_lds<NV, NT, P>(sW, ob + (a_left ? fwd0 : bwd0), a_left ? stride : -stride, t, WA);
+      const int ob = (a_left ? fc.left_elem() : fc.right_elem()) * ES;
+      nfb += trace_lds<NV, NTP, P>(sW, ob + (a_left ? fwd0 : bwd0), a_left ? stride : -stride, t, WA);
     }
     if (a_left && fc.right_local) {
-      nfb += trace_lds<NV, NT, P>(sW, fc.right_elem() * NPE + bwd0, -stride, t, WB);
+      nfb += trace_lds<NV, NTP, P>(sW, fc.right_elem() * ES + bwd0, -stride, t, WB);
     } else {
       const long long ge = a_left ? fc.right_global() : fc.left_global();
       if (ge >= 0) {
@@ -785,7 +790,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
         double Wn[NV];
         double Wp[NV];  // this node's primitives at the start of the stage (Newton start)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Wp[v] = sW[v * NT + tid];
+        for (int v = 0; v < NV; ++v) Wp[v] = sW[v * NTP + ln];
         const int st = con2prim<EOS, DIM>(Un, Wn, q, Wp, !changed);
         count_c2p(counter_slot(a.cnt), st, e);
 #pragma unroll
