@@ -33,6 +33,8 @@ RHS_CASES = [
     ("kh_tm", {"n_elem": (12, 10, 1)}),
     ("kh_tm", {"n_elem": (9, 7, 1), "c2p": wl.C2P_BRENT}),
     ("kh_tm", {"n_elem": (11, 6, 1), "p": 1}),
+    # c = 2: Theta / c^2 in [1/4, 5/2] straddles the 1/3 where the TM enthalpy form switches
+    ("kh_tm", {"n_elem": (10, 7, 1), "c": 2.0}),
     ("kh_ideal", {"n_elem": (10, 9, 1)}),
     ("kh_ideal", {"n_elem": (10, 9, 1), "p": 3}),
     ("kh_ideal", {"n_elem": (13, 5, 1), "p": 0}),
@@ -188,6 +190,7 @@ def test_enforce_matches_oracle(dim, p, n_elem):
 @pytest.mark.parametrize("kind,over,nsteps", [("kh_tm", {"n_elem": (12, 10, 1)}, 1),
                                               ("kh_tm", {"n_elem": (12, 10, 1)}, 4),
                                               ("kh_tm", {"n_elem": (12, 10, 1), "c2p": wl.C2P_CUBIC}, 4),
+                                              ("kh_tm", {"n_elem": (10, 7, 1), "c": 2.0}, 3),
                                               ("kh_ideal", {"n_elem": (10, 9, 1)}, 5),
                                               ("wave1d", {}, 10),
                                               ("random3d", {"n_elem": (5, 4, 3)}, 1)])
