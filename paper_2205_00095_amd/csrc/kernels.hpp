@@ -718,6 +718,33 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
 #pragma unroll
     for (int v = 0; v < NV; ++v) sFh[v * FPB + fc.fidx] = Fh[v];
   }
+  // lift weights (2/dx_d)(1/w_i) l_i(+-1) of this node, fetched (per-lane table loads)
+  // and formed before the barrier so that their latency overlaps the wait
+  double cpl[DIM], cml[DIM];
+  if constexpr (PREC == PREC_FP64) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int id = node_coord<N1>(node, d);
+      const double sc = m.two_dx[d] * t.iw[id];
+      cpl[d] = sc * t.lp[id];
+      cml[d] = sc * t.lm[id];
+      pin_reg(cpl[d]);
+      pin_reg(cml[d]);
+    }
+  }
+  // the epilogue's state loads, issued before the barrier (inactive lanes read element 0)
+  double Ukv[NV], U0v[NV];
+  const bool need_u0 = MODE == MODE_STAGE && (a.ca != 0.0 || a.za != 0.0);
+  if constexpr (MODE == MODE_STAGE) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ukv[v] = a.Uk[v * ntot + g];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U0v[v] = 0.0;
+    if (need_u0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) U0v[v] = a.Un[v * ntot + g];
+    }
+  }
   // trace fallbacks: one atomic per wave that saw any (all lanes are active here)
   static_assert(2 * ((FPB + NT - 1) / NT) < 16, "per-lane fallback count fits wave_sum16");
   {
@@ -736,7 +763,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if constexpr (PREC == PREC_FP64) {
-        R[v] -= m.two_dx[d] * t.iw[id] * (t.lp[id] * sFh[v * FPB + ip] - t.lm[id] * sFh[v * FPB + im]);
+        R[v] -= cpl[d] * sFh[v * FPB + ip] - cml[d] * sFh[v * FPB + im];
       } else {
         const double ref = sFref[((d * NV + v) * EPB + el) * NFP + pt];
         const float fpv = (float)(sFh[v * FPB + ip] - ref);
@@ -758,12 +785,11 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     }
   } else {
     double Un[NV], U0[NV];  // U^(k+1), U^n
-    const bool need_u0 = a.ca != 0.0 || a.za != 0.0;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) U0[v] = (act && need_u0) ? a.Un[v * ntot + g] : 0.0;
+    for (int v = 0; v < NV; ++v) U0[v] = act ? U0v[v] : 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double uk = act ? a.Uk[v * ntot + g] : 1.0;
+      const double uk = act ? Ukv[v] : 1.0;
       Un[v] = a.ca * U0[v] + a.cb * (uk + a.dt * R[v]);
     }
     if (a.Pout && act) {
