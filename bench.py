@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # instruction per SIMD every 4 cycles (16 lanes) -- the FP64 vector peak of
 # 78.6 TFLOP/s is this rate with every instruction an FMA
 SIMDS, CLOCK_HZ, VALU_CYCLES_PER_WAVE_INST = 1024, 2.4e9, 4.0
+FP64_VECTOR_PEAK = 78.6e12  # FLOP/s, MI355X published FP64 vector rate
 
 
 def _stage_bytes_per_dof(nvar: int) -> float:
@@ -274,7 +275,9 @@ def other_configs():
         d = solver.diagnostics()
         dofs = wl.n_dof(cfg)
         stages = 3 * (n + warm)
+        bpd = _stage_bytes_per_dof(wl.n_var(cfg))
         out[kind] = {"dof": dofs, "steps": n, "dof_stage_per_s": dofs * n * 3 / sec, "stage_us": sec / (3 * n) * 1e6,
+                     "algorithmic_bytes_per_dof": bpd, "hbm_frac": bpd * dofs * n * 3 / sec / (HBM_PEAK_GBS * 1e9),
                      "precision": "fp32-contraction" if cfg["precision"] == wl.FP32_CONTRACT else "fp64",
                      "per_stage": {k: d[k] / stages for k in ("smoothed", "flagged", "trace_fallback", "c2p_fail",
                                                             "bad_average")}}
@@ -460,6 +463,13 @@ def main(argv=None):
             out["roofline"]["valu"] = {
                 "insts_per_dof": prof["valu_insts_per_wave"], "f64_insts_per_dof": prof.get("f64_insts_per_wave"),
                 "issue_bound_us": issue_s * 1e6, "issue_frac": issue_s / stage_s}
+            if "mul_f64_per_wave" in prof:
+                # FP64 operations per DOF (an FMA counts two; every lane counted, so an upper
+                # bound where lanes idle) against the FP64 vector peak
+                flops = 2.0 * prof["fma_f64_per_wave"] + prof["mul_f64_per_wave"] + prof["add_f64_per_wave"]
+                out["roofline"]["valu"].update({
+                    "f64_flops_per_dof": flops, "f64_tflops": flops * dofs / stage_s / 1e12,
+                    "f64_peak_frac": flops * dofs / stage_s / FP64_VECTOR_PEAK})
     if not args.no_extras and args.workload == "kh_tm":
         extras = {}
         cfg3, s64, U64 = _setup("kh_tm_fp32", precision=wl.FP64)
