@@ -386,8 +386,8 @@ def main(argv=None):
                     help="also run one plain device copy of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design, not an implementation.", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is described in the design notes, not implemented.", file=sys.stderr)
         return 2
 
     import torch

@@ -2,8 +2,8 @@
 and vs central finite differences.
 
 Bars: vector-Jacobian products agree with the oracle's reverse mode to 1e-9
-normwise relative per component on smooth data (the benchmark spec asks 1e-6; the
-implicit-function-theorem and hand-reversed HLL reach rounding level); the
+normwise relative per component on smooth data (1e-6 would be the gradient
+bar; the implicit-function-theorem and hand-reversed HLL reach rounding level); the
 trajectory gradient of J = int v_y^2 dA agrees with central differences to
 1e-6 per direction, relative to max(|<g, v>|, 1e-3 |g|) (best of a step sweep)."""
 import numpy as np
