@@ -367,7 +367,9 @@ __host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, dou
 // the TM EOS and C2P_NEWTON it starts three Newton steps on the cubic, accepted when
 // the last step is below 1e-9 W and the iterate lies on the branch of the largest
 // root (f' > 0 beyond the inflection point); otherwise, and without Wprev, the
-// analytic root with one Newton polish.  Both give the same root to rounding.
+// analytic root with one Newton polish.  Both give the same root to rounding.  With
+// the ideal EOS and C2P_NEWTON it is the start of the Newton iteration on the quartic
+// (any start in (0, 1) converges to its one root there; the stop rule is unchanged).
 // known_admissible: the caller has evaluated admissible<DIM>(U) (the same expression)
 // and it held, so the test is skipped.
 template <int EOS, int DIM>
@@ -442,8 +444,18 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
                             ((al + 3.0) * ape - 4.0 * (al + 1.0));
           w = k1 * xi + k3 * xi * xi * xi;
         } else {
-          const double b = xi / eta;
-          w = b / (1.0 + sqrt(1.0 - b * b));
+          w = 0.0;
+          if (Wprev != nullptr) {
+            // start from the previous stage's root: w = |u| / (c (gamma + 1))
+            double u2 = 0.0;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) u2 += Wprev[1 + j] * Wprev[1 + j];
+            w = sqrt_pos(u2) * q.inv_c / (sqrt_pos(1.0 + u2 * q.inv_c2) + 1.0);
+          }
+          if (!(w > 0.0 && w < 1.0)) {
+            const double b = xi / eta;
+            w = b / (1.0 + sqrt(1.0 - b * b));
+          }
           bool conv = false;
           for (int it = 0; it < 30; ++it) {
             const double Pw = (((A * w - B) * w + C) * w - Dd) * w + A;
