@@ -554,20 +554,17 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
       if (status == C2P_OK) status = C2P_BADP;
     }
   }
-  if (status != C2P_OK && status != C2P_NOCONV) {
+  // the floor state at rest, exactly (also when the momentum itself is not finite)
+  const bool floor = (status != C2P_OK && status != C2P_NOCONV) ||
+                     (status == C2P_NOCONV && (!(P > 0.0) || !isfinite(P) || !isfinite(rho) || !isfinite(gb)));
+  if (floor) {
     rho = kRhoFloor;
     P = kPFloor * q.c2;
-    gb = 0.0;
-  }
-  if (status == C2P_NOCONV && (!(P > 0.0) || !isfinite(P) || !isfinite(rho) || !isfinite(gb))) {
-    rho = kRhoFloor;
-    P = kPFloor * q.c2;
-    gb = 0.0;
   }
   W[0] = rho;
   const double scale = gb * q.c * iS;
 #pragma unroll
-  for (int j = 0; j < DIM; ++j) W[1 + j] = scale * U[1 + j];
+  for (int j = 0; j < DIM; ++j) W[1 + j] = floor ? 0.0 : scale * U[1 + j];
   W[NV - 1] = P;
   return status;
 }
