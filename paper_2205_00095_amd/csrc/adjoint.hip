@@ -133,9 +133,14 @@ int step_tape(dg_ctx* c, double* U, double dt, double* tape, const char* what, b
   return hipcheck(c, L_element(c, MODE_STAGE, a), what);
 }
 
-// Reverse of one taped step: lam_n = (dU^{n+1}/dU^n)^T lam_next.
+// Reverse of one taped step: lam_n = (dU^{n+1}/dU^n)^T lam_next.  In a reverse sweep
+// over consecutive steps, pre_applied says that lam_next is already the adjoint of this
+// step's last pre-operator state (the operator's adjoint was fused into the next step's
+// first reverse stage), and prev_tape, when given, is the previous step's tape, whose
+// last operator's adjoint is fused into this step's first reverse stage (so lam_n is
+// then the adjoint of that step's last pre-operator state).
 int step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_next, double* lam_n,
-                  const char* what) {
+                  const char* what, bool pre_applied = false, const double* prev_tape = nullptr) {
   const size_t S = state_doubles(c);
   const double* W0 = tape;
   const double* W1 = tape + S;
@@ -154,7 +159,7 @@ int step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_ne
   // the operator after stage 3, when it acted: mua = Pi'(P3)^T lam_next (else
   // nothing is written and stage 3 reads lam_next)
   a.lam = lam_next;
-  if (phys) {
+  if (phys && !pre_applied) {
     if ((r = hipcheck(c, L_enforce_vjp(c, P3, lam_next, mua, flags + 2), what))) return r;
     a.lam_alt = mua;
     a.lam_sel = flags + 2;
@@ -170,8 +175,12 @@ int step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_ne
   a.W = W1; a.lam = mub; a.out = mu1; a.lamn_init = 0; a.ca = 0.75; a.cb = 0.25; a.Pprev = phys ? P1 : nullptr;
   a.pflag = flags;
   if ((r = hipcheck(c, L_vjp(c, VJP_STAGE, a), what))) return r;
-  // stage 1: U1 = Pi(U^n + dt R(U^n))
+  // stage 1: U1 = Pi(U^n + dt R(U^n)); U^n = Pi(P3 of the previous step) when prev_tape is given
   a.W = W0; a.lam = mu1; a.out = lam_n; a.ca = 0.0; a.cb = 1.0; a.Pprev = nullptr; a.pflag = nullptr;
+  if (phys && prev_tape) {
+    a.Ppost = prev_tape + 5 * S;
+    a.postflag = tape_flags(prev_tape, c) + 2;
+  }
   return hipcheck(c, L_vjp(c, VJP_STAGE, a), what);
 }
 
@@ -237,7 +246,9 @@ int dg_ssprk3_run_vjp_tape(dg_ctx* c, const double* tapes, double dt, int nsteps
   if (r) return r;
   const size_t T = tape_doubles(c);
   for (int s = nsteps - 1; s >= 0; --s) {
-    if ((r = step_vjp_tape(c, tapes + (size_t)s * T, dt, lam, lam, "dg_ssprk3_run_vjp_tape"))) return r;
+    const double* prev = s > 0 ? tapes + (size_t)(s - 1) * T : nullptr;
+    if ((r = step_vjp_tape(c, tapes + (size_t)s * T, dt, lam, lam, "dg_ssprk3_run_vjp_tape", s < nsteps - 1, prev)))
+      return r;
   }
   return finish(c, "dg_ssprk3_run_vjp_tape");
 }

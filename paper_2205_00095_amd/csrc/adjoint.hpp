@@ -27,6 +27,11 @@ struct VjpArgs {
   double* out;          // lambda_U (plain); previous stage's adjoint or lambda_n (stage)
   double* lamn;         // running adjoint of U^n (stage mode)
   const double* Pprev;  // pre-operator state of the previous stage (stage mode), or null
+  // first stage of a step (Pprev null): the output lambda_n is U^n's adjoint, U^n = Pi(Ppost)
+  // the previous step's last stage output; with Ppost set the output is Pi'(Ppost)^T lambda_n,
+  // the adjoint of that pre-operator state (the operator's adjoint fused into this launch)
+  const double* Ppost;
+  const unsigned* postflag;  // that operator changed nothing when *postflag == 0 (may be null)
   double ca, cb, dt;
   int lamn_init;        // 1: lamn is treated as zero on input
   MeshArgs m;
@@ -462,9 +467,21 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
           a.lamn[v * ntot + g] = acc[v];
         }
       }
-    } else if (act) {
+    } else {
+      double tot[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = acc[v] + lp[v];
+      for (int v = 0; v < NV; ++v) tot[v] = acc[v] + lp[v];
+      if (a.Ppost && (!a.postflag || *a.postflag != 0u)) {
+        double Pn[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Pn[v] = act ? a.Ppost[v * ntot + g] : 1.0;
+        __syncthreads();
+        physicality_vjp_block<DIM, P, NT, EPB>(Pn, tot, act, tid, el, node, t, q, sL, sred, sflag, svote);
+      }
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = tot[v];
+      }
     }
   }
 }

@@ -149,6 +149,36 @@ def test_enforce_active_branch_vjp_matches_autograd():
     assert float(err.max()) <= 1e-9, err.tolist()
 
 
+def test_run_vjp_tape_with_active_operator():
+    """A reverse sweep over taped steps whose stages trigger the physicality operator:
+    dg_ssprk3_run_vjp_tape, which fuses each step's last operator adjoint into the next
+    step's first reverse stage, equals the step-by-step reverse (each operator adjoint in
+    a launch of its own) and autograd through the oracle."""
+    from .test_gpu_parity import _flagged_mesh
+    st, U = _flagged_mesh(2, 2, (5, 4, 1), 77)
+    cfg = dict(dim=2, p=2, n_elem=(5, 4, 1), lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 0), eos=IDEAL,
+               gamma_ad=4 / 3, c=1.0, c2p=-1, precision=0, phys=True)
+    dt, nsteps = 1e-4, 3
+    lam = _lam(U.shape, 21)
+    Ur = U.clone().requires_grad_(True)
+    stats = {}
+    (ref,) = torch.autograd.grad(ots.run(Ur, dt, nsteps, st, phys=True, stats=stats), Ur, lam)
+    assert stats.get("smoothed", 0) > 0
+    s = _solver(cfg)
+    tapes = torch.empty((nsteps, s.tape_numel), dtype=torch.float64, device="cuda")
+    s.run_tape(U.cuda().contiguous(), dt, nsteps, tapes)
+    fused = lam.cuda().contiguous().clone()
+    s.run_vjp_tape(tapes, dt, nsteps, fused)
+    step = lam.cuda().contiguous().clone()
+    for k in reversed(range(nsteps)):
+        step = s.step_vjp_tape(tapes[k], dt, step)
+    err_step = rel_err_per_var(fused.cpu(), step.cpu())
+    err_ref = rel_err_per_var(fused.cpu(), ref)
+    print(f"fused vs step-by-step {err_step.tolist()}, vs oracle {err_ref.tolist()}", flush=True)
+    assert float(err_step.max()) <= 1e-13, err_step.tolist()
+    assert float(err_ref.max()) <= 1e-9, err_ref.tolist()
+
+
 def test_trajectory_gradient_matches_oracle():
     """dJ/d(v_y perturbation) through 4 steps (checkpoint every 3) vs the oracle's reverse mode."""
     from paper_2205_00095_amd.adjoint import vy2_after
