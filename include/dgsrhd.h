@@ -58,8 +58,9 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * Gauss-Legendre nodes with collocated quadrature (supported: dim 1..3,
  * p 0..3).  bc[d] applies to both ends of dimension d.  eos / gamma_ad /
  * c_light select the equation of state (Sec. 2.2).  c2p selects the recovery
- * solver of Sec. 3: ideal EOS NEWTON (Newton on the quartic in w, the default) or
- * QUARTIC (analytic); TM EOS CUBIC (analytic root of the cubic plus one Newton
+ * solver of Sec. 3: ideal EOS NEWTON (Newton on the quartic in w, the default;
+ * inside an SSP-RK stage started from the node's root of the previous stage,
+ * elsewhere from the beta_max bound) or QUARTIC (analytic); TM EOS CUBIC (analytic root of the cubic plus one Newton
  * step), BRENT (bracketed iteration) or NEWTON (the default: inside an SSP-RK
  * stage, three Newton steps on the same cubic started from the node's primitives
  * of the previous stage and accepted only when converged on the physical root,
