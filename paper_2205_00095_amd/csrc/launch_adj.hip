@@ -22,13 +22,15 @@ hipError_t run_vjp(const VjpArgs& a, hipStream_t s) {
 template <int DIM, int P>
 hipError_t vjp_by(int eos, int mode, const VjpArgs& a, hipStream_t s) {
   if (eos == EOS_IDEAL)
-    return mode == VJP_PLAIN ? run_vjp<DIM, P, EOS_IDEAL, VJP_PLAIN>(a, s) : run_vjp<DIM, P, EOS_IDEAL, VJP_STAGE>(a, s);
-  return mode == VJP_PLAIN ? run_vjp<DIM, P, EOS_TM, VJP_PLAIN>(a, s) : run_vjp<DIM, P, EOS_TM, VJP_STAGE>(a, s);
+    return mode == VJP_PLAIN ? run_vjp<DIM, P, EOS_IDEAL, VJP_PLAIN>(a, s)
+                             : run_vjp<DIM, P, EOS_IDEAL, VJP_STAGE>(a, s);
+  return mode == VJP_PLAIN ? run_vjp<DIM, P, EOS_TM, VJP_PLAIN>(a, s)
+                           : run_vjp<DIM, P, EOS_TM, VJP_STAGE>(a, s);
 }
 
 template <int DIM, int P>
-hipError_t run_enforce_vjp(const double* Pst, const double* lin, double* lout, const unsigned* flag, const MeshArgs& m, const Tables& t,
-                           const PhysParams& q, hipStream_t s) {
+hipError_t run_enforce_vjp(const double* Pst, const double* lin, double* lout, const unsigned* flag,
+                           const MeshArgs& m, const Tables& t, const PhysParams& q, hipStream_t s) {
   using G = Geo<DIM, P>;
   const int nb = (m.nelem + G::EPB - 1) / G::EPB;
   hipLaunchKernelGGL((k_enforce_vjp<DIM, P>), dim3(nb), dim3(G::NT), 0, s, Pst, lin, lout, m, t, q, flag);
@@ -50,9 +52,9 @@ hipError_t DG_CAT(launch_vjp_dim, DG_DIM)(int p, int eos, int mode, const VjpArg
   }
 }
 
-hipError_t DG_CAT(launch_enforce_vjp_dim, DG_DIM)(int p, const double* Pst, const double* lin, double* lout, const unsigned* flag,
-                                                  const MeshArgs& m, const Tables& t, const PhysParams& q,
-                                                  hipStream_t s) {
+hipError_t DG_CAT(launch_enforce_vjp_dim, DG_DIM)(int p, const double* Pst, const double* lin, double* lout,
+                                                  const unsigned* flag, const MeshArgs& m, const Tables& t,
+                                                  const PhysParams& q, hipStream_t s) {
   switch (p) {
     case 0: return run_enforce_vjp<DG_DIM, 0>(Pst, lin, lout, flag, m, t, q, s);
     case 1: return run_enforce_vjp<DG_DIM, 1>(Pst, lin, lout, flag, m, t, q, s);
