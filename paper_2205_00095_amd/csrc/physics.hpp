@@ -43,20 +43,6 @@ __host__ __device__ __forceinline__ double h_excess(double th, const PhysParams&
   }
 }
 
-// Sound speed squared: ideal c^2 Gamma Theta / h; Taub-Matthews
-// c^2 (3 Theta^2 + 5 Theta s) / (12 Theta^2 + 2 c^4 + 12 Theta s).
-template <int EOS>
-__host__ __device__ __forceinline__ double sound2(double th, double he, const PhysParams& q) {
-  if constexpr (EOS == EOS_IDEAL) {
-    return q.c2 * q.gam * th / (q.c2 + he);
-  } else {
-    const double s = sqrt(th * th + (4.0 / 9.0) * q.c4);
-    const double num = 3.0 * th * th + 5.0 * th * s;
-    const double den = 12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s;
-    return q.c2 * num / den;
-  }
-}
-
 // Component d of a DIM-vector stored from v[0], for a direction known only at run
 // time: a chain of selects over values.  An indexed access would move the array to
 // scratch memory, and so would the optimiser's folding of a select of two loads into
@@ -112,6 +98,8 @@ struct StateEval {
   double P;
   double th, he;  // Theta, h - c^2
   double sq;      // Taub-Matthews: sqrt(Theta^2 + 4/9 c^4)
+  double isq;     // Taub-Matthews: 1 / sq
+  double r;       // 1 / (rho (gamma + 1))
 };
 
 template <int EOS, int DIM>
@@ -131,8 +119,11 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
   if constexpr (EOS == EOS_IDEAL) {
     he = q.alpha * th;
     s.sq = 0.0;
+    s.isq = 0.0;
   } else {
-    s.sq = sqrt_pos(th * th + (4.0 / 9.0) * q.c4);
+    const double x = th * th + (4.0 / 9.0) * q.c4;  // > 0
+    s.isq = inv_sqrt(x);
+    s.sq = x * s.isq;
     // th^2 / (sq + 2/3 c^2) equals sq - 2/3 c^2; the difference costs no division and,
     // for Theta >= c^2 / 3, loses at most a factor 18 to cancellation (a few 1e-16 of he)
     const double a = (2.0 / 3.0) * q.c2;
@@ -154,6 +145,7 @@ __host__ __device__ __forceinline__ void eval_state(const double* W, const PhysP
   s.P = P;
   s.th = th;
   s.he = he;
+  s.r = r;
 }
 
 // Physical flux along direction d in (D, S, tau) variables (Eq. srhd_flux with the

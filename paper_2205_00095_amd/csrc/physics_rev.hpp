@@ -22,24 +22,6 @@ __host__ __device__ __forceinline__ double h_excess_d(double th, const PhysParam
   }
 }
 
-// d(c_s^2)/dTheta with c_s^2 written as a function of Theta alone
-template <int EOS>
-__host__ __device__ __forceinline__ double sound2_d(double th, const PhysParams& q, double sq = -1.0) {
-  if constexpr (EOS == EOS_IDEAL) {
-    // c^2 Gamma Theta / (c^2 + alpha Theta)
-    const double den = q.c2 + q.alpha * th;
-    return q.c2 * q.gam * q.c2 / (den * den);
-  } else {
-    const double s = sq >= 0.0 ? sq : sqrt(th * th + (4.0 / 9.0) * q.c4);
-    const double ds = th / s;
-    const double num = 3.0 * th * th + 5.0 * th * s;
-    const double den = 12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s;
-    const double dnum = 6.0 * th + 5.0 * s + 5.0 * th * ds;
-    const double dden = 24.0 * th + 12.0 * s + 12.0 * th * ds;
-    return q.c2 * (dnum * den - num * dden) / (den * den);
-  }
-}
-
 // Adjoint of eval_state: given adjoints of (U[0..NV), g2, ig, th, he) and of P
 // (returned through lam_W[NV-1]), accumulate into lam_W.  st is the forward
 // evaluation at W (its square roots and quotients are reused).
@@ -60,7 +42,7 @@ __host__ __device__ __forceinline__ void eval_state_rev(const double* W, const S
   const double D = st.U[0];
   const double hc = (q.c2 + he) * q.inv_c2;
   const double gH = g * rho * hc;
-  const double igp1 = 1.0 / (g + 1.0);
+  const double igp1 = rho * st.r;  // 1 / (g + 1)
   // ig = 1/g
   double lam_g = -lam_ig * ig * ig;
   // tau = D usq/(g+1) + g2 rho he - P
@@ -86,10 +68,11 @@ __host__ __device__ __forceinline__ void eval_state_rev(const double* W, const S
   // D = g rho
   lam_g += lam_D * rho;
   lam_rho += lam_D * g;
-  // he = h_excess(th)
-  lam_th += lam_he * h_excess_d<EOS>(th, q, st.sq);
+  // he = h_excess(th); Taub-Matthews: he = 5/2 th + 3/2 (sq - 2/3 c^2), d sq / d th = th / sq
+  if constexpr (EOS == EOS_IDEAL) lam_th += lam_he * q.alpha;
+  else lam_th += lam_he * (2.5 + 1.5 * th * st.isq);
   // th = P / rho
-  const double irho = 1.0 / rho;
+  const double irho = (g + 1.0) * st.r;  // 1 / rho
   lam_P += lam_th * irho;
   lam_rho += -lam_th * th * irho;
   // g = sqrt(g2)
@@ -111,16 +94,49 @@ __host__ __device__ __forceinline__ void eval_state_rev(const double* W, const P
   eval_state_rev<EOS, DIM>(W, st, q, lam_U, lam_g2, lam_ig, lam_th, lam_he, lam_W);
 }
 
+// The signal speeds of wavespeeds() with the intermediates their adjoint reuses:
+// lambda_pm = (vd gK pm root) inv, gK = gamma^2 K, root = sqrt(N X),
+// X = gK (c^2 - vd^2) + c^2 N, inv = 1 / (gK + N) (N, K as in wavespeeds_nd).
+struct SpeedParts {
+  double vd, N, K, gK, X, rr, root, inv, lm, lp;  // rr = 1 / root (0 when root = 0)
+};
+
+// Its inputs pass through opaque() so that the compiler recomputes these values where
+// the adjoint needs them instead of keeping the forward's copies live in between.
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void speed_parts(const double* W, const StateEval<EOS, DIM>& s, int d,
+                                                     const PhysParams& q, SpeedParts& p) {
+  const double th = opaque(s.th), g2 = opaque(s.g2);
+  if constexpr (EOS == EOS_IDEAL) {
+    p.N = q.gam * th;
+    p.K = q.c2 + (q.alpha - q.gam) * th;
+  } else {
+    const double sq = opaque(s.sq);
+    p.N = th * (3.0 * th + 5.0 * sq);
+    p.K = th * (9.0 * th + 7.0 * sq) + 2.0 * q.c4;
+  }
+  p.vd = comp<DIM>(W + 1, d) * opaque(s.ig);
+  p.gK = g2 * p.K;
+  p.X = p.gK * (q.c2 - p.vd * p.vd) + q.c2 * p.N;
+  const double nx = p.N * p.X;
+  p.rr = nx > 0.0 ? inv_sqrt(nx) : 0.0;
+  p.root = nx * p.rr;
+  p.inv = 1.0 / (p.gK + p.N);
+  p.lm = (p.vd * p.gK - p.root) * p.inv;
+  p.lp = (p.vd * p.gK + p.root) * p.inv;
+}
+
 // Adjoint of (U, F^d, lambda_-, lambda_+) of one primitive state along d.
 // lam_U, lam_F: adjoints of the conserved state and of the flux; lam_lm, lam_lp:
 // adjoints of the two signal speeds (pass 0 when unused).
 template <int EOS, int DIM>
-__host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, const StateEval<EOS, DIM>& s, int d,
-                                                              const PhysParams& q, const double* lam_U_in,
-                                                              const double* lam_F, double lam_lm, double lam_lp,
-                                                              bool with_speeds, double* lam_W) {
+__host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, const StateEval<EOS, DIM>& s,
+                                                              const SpeedParts& sp, int d, const PhysParams& q,
+                                                              const double* lam_U_in, const double* lam_F,
+                                                              double lam_lm, double lam_lp, bool with_speeds,
+                                                              double* lam_W) {
   constexpr int NV = DIM + 2;
-  const double vd = comp<DIM>(W + 1, d) * s.ig;
+  const double vd = sp.vd;
   double lam_U[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) lam_U[k] = lam_U_in[k];
@@ -135,33 +151,32 @@ __host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, c
   lam_vd += lam_F[NV - 1] * s.P;
   double lam_g2 = 0.0, lam_th = 0.0;
   if (with_speeds) {
-    double cs2;
+    // lambda_pm = (vd gK pm root) inv
+    const double lam_den = -(lam_lm * sp.lm + lam_lp * sp.lp) * sp.inv;  // inv = 1 / (gK + N)
+    const double lam_vdgK = (lam_lm + lam_lp) * sp.inv;
+    const double lam_root = (lam_lp - lam_lm) * sp.inv;
+    lam_vd += lam_vdgK * sp.gK;
+    double lam_gK = lam_vdgK * vd + lam_den;
+    double lam_N = lam_den;
+    if (sp.root > 0.0) {
+      // root = sqrt(N X), X = gK (c^2 - vd^2) + c^2 N
+      const double lam_NX = 0.5 * lam_root * sp.rr;
+      lam_N += lam_NX * sp.X;
+      const double lam_X = lam_NX * sp.N;
+      lam_gK += lam_X * (q.c2 - vd * vd);
+      lam_vd += -2.0 * vd * sp.gK * lam_X;
+      lam_N += q.c2 * lam_X;
+    }
+    // gK = gamma^2 K
+    lam_g2 += lam_gK * sp.K;
+    const double lam_K = lam_gK * s.g2;
+    // N, K as functions of Theta
     if constexpr (EOS == EOS_IDEAL) {
-      cs2 = q.c2 * q.gam * s.th / (q.c2 + s.he);
+      lam_th += q.gam * lam_N + (q.alpha - q.gam) * lam_K;
     } else {
-      const double th = s.th;
-      cs2 = q.c2 * (3.0 * th * th + 5.0 * th * s.sq) / (12.0 * th * th + 2.0 * q.c4 + 12.0 * th * s.sq);
+      const double th = s.th, ds = th * s.isq;  // d sq / d Theta
+      lam_th += lam_N * (6.0 * th + 5.0 * s.sq + 5.0 * th * ds) + lam_K * (18.0 * th + 7.0 * s.sq + 7.0 * th * ds);
     }
-    const double den = q.c2 - cs2;
-    const double sigma = cs2 / (s.g2 * den);
-    const double Qr = q.c2 - vd * vd + q.c2 * sigma;
-    const double root = sqrt(sigma * Qr);
-    const double inv = 1.0 / (1.0 + sigma);
-    // lm = (vd - root) inv ; lp = (vd + root) inv
-    lam_vd += (lam_lm + lam_lp) * inv;
-    const double lam_root = (lam_lp - lam_lm) * inv;
-    const double lam_inv = lam_lm * (vd - root) + lam_lp * (vd + root);
-    double lam_sigma = -lam_inv * inv * inv;
-    // root = sqrt(sigma Qr)
-    if (root > 0.0) {
-      const double lam_r2 = lam_root / (2.0 * root);
-      lam_sigma += lam_r2 * (Qr + q.c2 * sigma);
-      lam_vd += -lam_r2 * sigma * 2.0 * vd;
-    }
-    // sigma = cs2 / (g2 (c^2 - cs2))
-    const double lam_cs2 = lam_sigma * q.c2 / (s.g2 * den * den);
-    lam_g2 += -lam_sigma * sigma / s.g2;
-    lam_th += lam_cs2 * sound2_d<EOS>(s.th, q, s.sq);
   }
   // vd = u_d * ig
   comp_add<DIM>(lam_W + 1, d, lam_vd * s.ig);
@@ -177,7 +192,9 @@ __host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, i
                                                               double* lam_W) {
   StateEval<EOS, DIM> s;
   eval_state<EOS, DIM>(W, q, s);
-  state_flux_speed_rev<EOS, DIM>(W, s, d, q, lam_U_in, lam_F, lam_lm, lam_lp, with_speeds, lam_W);
+  SpeedParts sp;
+  speed_parts<EOS, DIM>(W, s, d, q, sp);
+  state_flux_speed_rev<EOS, DIM>(W, s, sp, d, q, lam_U_in, lam_F, lam_lm, lam_lp, with_speeds, lam_W);
 }
 
 // Adjoint of hll_flux(WL, WR, d): accumulates into lam_WL and lam_WR.
@@ -226,8 +243,17 @@ __host__ __device__ __forceinline__ void hll_flux_rev(const double* WL, const do
     if (lmL <= lmR) lam_lmL = lam_aL; else lam_lmR = lam_aL;
     if (lpL >= lpR) lam_lpL = lam_aR; else lam_lpR = lam_aR;
   }
-  if (need_L) state_flux_speed_rev<EOS, DIM>(WL, sL, d, q, lam_UL, lam_FL, lam_lmL, lam_lpL, speeds, lam_WL);
-  if (need_R) state_flux_speed_rev<EOS, DIM>(WR, sR, d, q, lam_UR, lam_FR, lam_lmR, lam_lpR, speeds, lam_WR);
+  // the speed intermediates are recomputed per side rather than kept live from above
+  if (need_L) {
+    SpeedParts p;
+    speed_parts<EOS, DIM>(WL, sL, d, q, p);
+    state_flux_speed_rev<EOS, DIM>(WL, sL, p, d, q, lam_UL, lam_FL, lam_lmL, lam_lpL, speeds, lam_WL);
+  }
+  if (need_R) {
+    SpeedParts p;
+    speed_parts<EOS, DIM>(WR, sR, d, q, p);
+    state_flux_speed_rev<EOS, DIM>(WR, sR, p, d, q, lam_UR, lam_FR, lam_lmR, lam_lpR, speeds, lam_WR);
+  }
 }
 
 // J[r][c] = dU_r / dW_c at the primitive state W (Eq. primitive_to_conserved).
