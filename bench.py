@@ -350,8 +350,10 @@ def kh_growth(nx=256, orders=(0, 1, 2), t_end=3.0, sample_dt=0.05):
     return {"diagnostic": "fit of log <v_y^2> = A + r t over t in [1.5, 3]", "rows": out}
 
 
-def cpu_baseline(kind="kh_tm", steps=3):
-    """The oracle as it stands, on the host cores, for `steps` SSP-RK3 steps of the full mesh."""
+def cpu_baseline(kind="kh_tm", steps=3, seconds=10.0):
+    """The oracle as it stands, on the host cores: `steps` SSP-RK3 steps of the full mesh,
+    then as many more as fill about `seconds` of wall time in total (a bounded sample)."""
+    import math
     import torch
     from oracle import srhd, timestep
     from oracle.setup import Setup
@@ -361,8 +363,14 @@ def cpu_baseline(kind="kh_tm", steps=3):
     rho, v, P = (torch.from_numpy(a) for a in wl.initial_primitives(cfg))
     U = srhd.prim3_to_cons(rho, v, P, st).reshape((st.nvar,) + wl.field_shape(cfg))
     t0 = time.perf_counter()
-    timestep.run(U, cfg["dt"], steps, st)
+    U = timestep.run(U, cfg["dt"], steps, st)
     dt = time.perf_counter() - t0
+    more = max(0, math.ceil((seconds - dt) / (dt / steps))) if steps > 0 else 0
+    if more:
+        t1 = time.perf_counter()
+        timestep.run(U, cfg["dt"], more, st)
+        dt += time.perf_counter() - t1
+        steps += more
     dofs = wl.n_dof(cfg)
     return {"value": dofs * steps * 3 / dt, "unit": "DOF-stage/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
@@ -378,6 +386,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="kh_tm")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32, adjoint and CPU legs")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall time the CPU oracle sample fills (after --cpu-steps steps)")
     ap.add_argument("--con2prim-study", action="store_true",
                     help="only run the recovery-solver study of the paper's Sec. 3.3 and print its JSON")
     ap.add_argument("--kh-growth", action="store_true",
@@ -503,7 +513,7 @@ def main(argv=None):
         extras["other_configs"] = other_configs()
         extras["adjoint"] = adjoint_ratio()
         out.update(extras)
-        out["cpu_baseline"] = cpu_baseline("kh_tm", args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline("kh_tm", args.cpu_steps, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
