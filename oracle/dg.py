@@ -14,7 +14,7 @@ Steps, in the order of Sec. 2.3:
     Reading: a trace with rho <= 0 or P <= 0 is replaced by the primitive
     state of the node nearest to that face on the same line (counted);
  4. exterior states: periodic neighbour, or outflow (exterior = interior);
- 5. HLL numerical flux at every face point, Eq. (quad-surface-flux);
+ 5. HLL (or HLLC) numerical flux at every face point, Eq. (quad-surface-flux);
  6. lift with the inverse mass:
         S_i = -sum_d (2/dx_d)(1/w_{i_d}) [l_{i_d}(+1) Fhat^+ - l_{i_d}(-1) Fhat^-];
  7. R = V + S  (= dU/dt).
@@ -32,7 +32,7 @@ import torch
 from . import basis
 from .con2prim import con2prim
 from .setup import PERIODIC
-from .srhd import flux, hll
+from .srhd import face_flux, flux
 
 
 def _t(a):
@@ -91,7 +91,7 @@ def surface_term(W, st, stats=None):
         Wm, Wp, nb = traces(W, d, st)
         nfb += nb
         WL, WR = face_states(Wm, Wp, d, st)
-        Fh = hll(WL, WR, d, st)
+        Fh = face_flux(WL, WR, d, st)
         n = W.shape[ea]
         Fplus = Fh.narrow(ea, 1, n).unsqueeze(ax)
         Fminus = Fh.narrow(ea, 0, n).unsqueeze(ax)

@@ -6,6 +6,7 @@ from dataclasses import dataclass, field
 PERIODIC, OUTFLOW = 0, 1
 IDEAL, TM = 0, 1
 NEWTON, QUARTIC, CUBIC, BRENT = 0, 1, 2, 3
+HLL, HLLC = 0, 1
 
 
 @dataclass
@@ -21,13 +22,15 @@ class Setup:
     c: float = 1.0
     c2p: int = -1            # -1: the paper's default solver for the EOS (Newton / cubic)
     phys_eps: float = 1e-12
+    flux: int = HLL          # numerical flux: HLL or HLLC (Sec. 2.4)
     extra: dict = field(default_factory=dict)
 
     @staticmethod
     def from_config(cfg: dict) -> "Setup":
         return Setup(dim=cfg["dim"], p=cfg["p"], n_elem=tuple(cfg["n_elem"]), lo=tuple(cfg["lo"]),
                      hi=tuple(cfg["hi"]), bc=tuple(cfg["bc"]), eos=cfg["eos"],
-                     gamma_ad=cfg["gamma_ad"], c=cfg["c"], c2p=cfg["c2p"])
+                     gamma_ad=cfg["gamma_ad"], c=cfg["c"], c2p=cfg["c2p"],
+                     flux=cfg.get("flux", HLL))
 
     @property
     def nvar(self) -> int:

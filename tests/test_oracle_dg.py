@@ -139,3 +139,23 @@ def test_outflow_boundary_face_uses_interior_flux():
     f0 = srhd.flux(Wc[:, :1], 0, st)[:, 0]
     f01 = srhd.hll(Wc[:, 0, None], Wc[:, 1, None], 0, st)[:, 0]
     assert torch.allclose(R[:, 0], -(f01 - f0) / st.dx(0), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim,p,eos", [(1, 2, IDEAL), (2, 2, TM), (3, 1, IDEAL)])
+def test_hllc_rhs_uniform_zero_and_conservative(dim, p, eos):
+    """The operator with the HLLC flux: zero for a uniform state, discretely conservative
+    on a periodic mesh."""
+    from oracle.setup import HLLC
+    st = Setup(dim=dim, p=p, n_elem=(4, 3, 2)[:dim] + (1,) * (3 - dim), eos=eos, flux=HLLC)
+    rng = np.random.default_rng(40 + dim)
+    U0 = _random_state(Setup(dim=dim, p=0, eos=eos), rng)
+    U = U0.reshape(st.nvar, *([1] * 6)).expand((st.nvar,) + st.shape()).clone()
+    R = dg.rhs(U, st)
+    W, _ = cp.con2prim(U, st)
+    fmax = max(float(srhd.flux(W, d, st).abs().max()) * 2 / st.dx(d) for d in range(dim))
+    assert float(R.abs().max()) <= 1e-13 * fmax * (p + 1) ** 2
+    U = _random_state(st, rng)
+    wR = dg.rhs(U, st) * dg.elem_weights(st)
+    tot = wR.sum((1, 2, 3, 4, 5, 6))
+    scale = wR.abs().sum((1, 2, 3, 4, 5, 6))
+    assert float((tot.abs() / scale).max()) < 1e-13
