@@ -14,8 +14,8 @@ physicality operator on.  Extra results on the same JSON line:
                  20) relative to the forward run, 128x128 p=2 ideal-gas mesh;
   roofline       the stage kernel against HBM, from algorithmic bytes per
                  DOF-stage (read U^(k), read U^n in stages 2-3, write U^(k+1)).
-  paper_sweep    the paper's KH performance grid: p = 0, 1, 2 with RK1, SSPRK2,
-                 SSPRK3 on 256x512 .. 1024x2048 meshes (ideal EOS).
+  paper_sweep    the paper's KH performance grid: HLL and HLLC, p = 0, 1, 2 with
+                 RK1, SSPRK2, SSPRK3 on 256x512 .. 1024x2048 meshes (ideal EOS).
   cpu_baseline   the FP64 CPU oracle on the host cores for a bounded sample.
 """
 from __future__ import annotations
@@ -287,47 +287,50 @@ def other_configs():
 
 
 def paper_sweep(target_s=0.15):
-    """The paper's KH performance grid (Sec. 4) on one MI355X: basis orders 0, 1, 2 with
-    RK1, SSPRK2, SSPRK3 on nx x 2nx meshes, nx = 256, 512, 1024 (ideal EOS, HLL)."""
+    """The paper's KH performance grid (Sec. 4) on one MI355X: the HLL and HLLC fluxes,
+    basis orders 0, 1, 2 with RK1, SSPRK2, SSPRK3 on nx x 2nx meshes, nx = 256, 512,
+    1024 (ideal EOS)."""
     import torch
     from paper_2205_00095_amd import workloads as wl
     rows = []
-    for p in (0, 1, 2):
-        for nx in (256, 512, 1024):
-            cfg, solver, U = _setup("kh_paper", nx=nx, p=p)
-            order = cfg["rk_order"]
-            dofs = wl.n_dof(cfg)
-            solver.run(U, cfg["dt"], 3, order=order)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            solver.run(U, cfg["dt"], 5, order=order)
-            torch.cuda.synchronize()
-            per_step = (time.perf_counter() - t0) / 5
-            n = max(10, int(target_s / per_step))
-            stream = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            solver.run(U, cfg["dt"], n, order=order)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            sec = e0.elapsed_time(e1) / 1e3
-            rows.append({"p": p, "rk_order": order, "mesh": f"{nx}x{2 * nx}", "dof": dofs, "steps": n,
-                         "dof_stage_per_s": dofs * n * order / sec, "stage_us": sec / (n * order) * 1e6})
-            solver.close()
-            del U
-    return {"workload": "kh_paper: one shear interface, ideal Gamma=4/3, HLL, physicality operator on, FP64",
-            "rows": rows}
+    grid = [(f, p, n) for f in (wl.FLUX_HLL, wl.FLUX_HLLC) for p in (0, 1, 2) for n in (256, 512, 1024)]
+    for flux, p, nx in grid:
+        cfg, solver, U = _setup("kh_paper", nx=nx, p=p, flux=flux)
+        order = cfg["rk_order"]
+        dofs = wl.n_dof(cfg)
+        solver.run(U, cfg["dt"], 3, order=order)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.run(U, cfg["dt"], 5, order=order)
+        torch.cuda.synchronize()
+        per_step = (time.perf_counter() - t0) / 5
+        n = max(10, int(target_s / per_step))
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        solver.run(U, cfg["dt"], n, order=order)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        rows.append({"flux": "HLLC" if flux == wl.FLUX_HLLC else "HLL", "p": p, "rk_order": order,
+                     "mesh": f"{nx}x{2 * nx}", "dof": dofs, "steps": n,
+                     "dof_stage_per_s": dofs * n * order / sec, "stage_us": sec / (n * order) * 1e6})
+        solver.close()
+        del U
+    return {"workload": "kh_paper: one shear interface, ideal Gamma=4/3, HLL and HLLC, physicality operator on, "
+                        "FP64", "rows": rows}
 
 
 def kh_growth(nx=256, orders=(0, 1, 2), t_end=3.0, sample_dt=0.05):
     """Growth rate r of <v_y^2> from a least-squares fit of log <v_y^2> = A + r t over
-    t in [1.5, 3] (the paper's KH diagnostic, Sec. 4), per basis order on an nx x 2nx mesh."""
+    t in [1.5, 3] (the paper's KH diagnostic, Sec. 4), per flux (HLL, HLLC) and basis
+    order on an nx x 2nx mesh."""
     import numpy as np
     import torch
     from paper_2205_00095_amd import workloads as wl
     out = []
-    for p in orders:
-        cfg, solver, U = _setup("kh_paper", nx=nx, p=p)
+    for flux, p in [(f, p) for f in (wl.FLUX_HLL, wl.FLUX_HLLC) for p in orders]:
+        cfg, solver, U = _setup("kh_paper", nx=nx, p=p, flux=flux)
         order, dt = cfg["rk_order"], cfg["dt"]
         area = (cfg["hi"][0] - cfg["lo"][0]) * (cfg["hi"][1] - cfg["lo"][1])
         every = max(1, int(round(sample_dt / dt)))
@@ -343,7 +346,8 @@ def kh_growth(nx=256, orders=(0, 1, 2), t_end=3.0, sample_dt=0.05):
         ts, vals = np.array(ts), np.array(vals)
         sel = (ts >= 1.5) & (ts <= 3.0)
         r, A = np.polyfit(ts[sel], np.log(vals[sel]), 1)
-        out.append({"p": p, "rk_order": order, "mesh": f"{nx}x{2 * nx}", "dof": wl.n_dof(cfg),
+        out.append({"flux": "HLLC" if flux == wl.FLUX_HLLC else "HLL", "p": p, "rk_order": order,
+                    "mesh": f"{nx}x{2 * nx}", "dof": wl.n_dof(cfg),
                     "growth_rate": float(r), "vy2_t0": float(vals[0]), "vy2_t3": float(vals[sel][-1]),
                     "steps": int(round(t / dt)), "wall_s": wall, "diagnostics": solver.diagnostics()})
         solver.close()

@@ -51,6 +51,7 @@ enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1 };
 enum { DG_EOS_IDEAL = 0, DG_EOS_TM = 1 };
 enum { DG_C2P_DEFAULT = -1, DG_C2P_NEWTON = 0, DG_C2P_QUARTIC = 1, DG_C2P_CUBIC = 2, DG_C2P_BRENT = 3 };
 enum { DG_FP64 = 0, DG_FP32_CONTRACT = 1 };
+enum { DG_FLUX_HLL = 0, DG_FLUX_HLLC = 1 };
 enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
 
 /* Mesh and method description.  Cartesian mesh of n_elem[d] equal elements on
@@ -68,7 +69,12 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * evaluates the volume, trace and lift contractions in FP32 on deviations from
  * a per-element FP64 reference; everything else stays FP64.  phys = 1 applies
  * the physicality-enforcing operator (Sec. 2.5) after every SSP-RK stage, with
- * relative margin phys_eps (0 selects 1e-12). */
+ * relative margin phys_eps (0 selects 1e-12).  flux selects the numerical flux at
+ * the faces (Sec. 2.4): DG_FLUX_HLL (0, the default when the field is zeroed) or
+ * DG_FLUX_HLLC, the HLLC solver of Mignone & Bodo (2005) with one contact wave
+ * inside the HLL fan (exact on isolated contacts, including tangential-velocity
+ * jumps); the adjoint entry points (the taped steps and every *_vjp* call)
+ * support HLL only and return DG_EINVAL for HLLC. */
 typedef struct {
   int dim, p;
   int n_elem[3];
@@ -82,6 +88,7 @@ typedef struct {
   int phys;
   double phys_eps;
   int sync_mode;
+  int flux;
 } dg_mesh_desc;
 
 typedef struct {

@@ -28,6 +28,7 @@ class MeshDesc(ctypes.Structure):
         ("c2p", ctypes.c_int), ("precision", ctypes.c_int),
         ("phys", ctypes.c_int), ("phys_eps", ctypes.c_double),
         ("sync_mode", ctypes.c_int),
+        ("flux", ctypes.c_int),
     ]
 
 

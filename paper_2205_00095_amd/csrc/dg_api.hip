@@ -146,10 +146,10 @@ void gl_tables(int p, int dim, Tables& t) {
 }
 
 hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a) {
-  const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos, prec = c->desc.precision;
-  if (dim == 1) return launch_element_dim1(p, eos, prec, mode, a, c->stream);
-  if (dim == 2) return launch_element_dim2(p, eos, prec, mode, a, c->stream);
-  return launch_element_dim3(p, eos, prec, mode, a, c->stream);
+  const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos, prec = c->desc.precision, fl = c->desc.flux;
+  if (dim == 1) return launch_element_dim1(p, eos, prec, mode, fl, a, c->stream);
+  if (dim == 2) return launch_element_dim2(p, eos, prec, mode, fl, a, c->stream);
+  return launch_element_dim3(p, eos, prec, mode, fl, a, c->stream);
 }
 
 hipError_t L_con2prim(dg_ctx* c, const double* U, double* W) {
@@ -240,6 +240,7 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   if (d.eos == DG_EOS_TM && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_CUBIC && d.c2p != DG_C2P_BRENT)
     return bad("TM EOS needs the Newton, cubic or Brent solver");
   if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT) return bad("unknown precision");
+  if (d.flux != DG_FLUX_HLL && d.flux != DG_FLUX_HLLC) return bad("flux must be HLL or HLLC");
   if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
   const long long nelem = (long long)d.n_elem[0] * d.n_elem[1] * d.n_elem[2];
   if (nelem > (1ll << 30)) return bad("mesh too large");

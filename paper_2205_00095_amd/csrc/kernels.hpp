@@ -588,7 +588,7 @@ __device__ __forceinline__ void pin_reg(float& x) { asm volatile("" : "+v"(x)); 
 template <int DIM, int P>
 constexpr int elem_min_waves() { return (DIM == 2 && P >= 2) ? 5 : 1; }
 
-template <int DIM, int P, int EOS, int PREC, int MODE>
+template <int DIM, int P, int EOS, int PREC, int MODE, int FLUX>
 __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) void k_element(ElemArgs a) {
   using T = TileGeo<DIM, P>;
   constexpr int N1 = T::N1, NPE = T::NPE, NV = T::NV, NT = T::NT, EPB = T::EPB;
@@ -722,7 +722,10 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
       WR[v] = a_left ? WB[v] : WA[v];
     }
     double Fh[NV];
-    hll_flux<EOS, DIM>(WL, WR, d, q, Fh);
+    if constexpr (FLUX == FLUX_HLLC)
+      hllc_flux<EOS, DIM>(WL, WR, d, q, Fh);
+    else
+      hll_flux<EOS, DIM>(WL, WR, d, q, Fh);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sFh[v * FPB + fc.fidx] = Fh[v];
   }

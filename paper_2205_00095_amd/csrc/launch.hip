@@ -11,31 +11,37 @@ namespace dgsrhd {
 
 namespace {
 
-template <int DIM, int P, int EOS, int PREC, int MODE>
+template <int DIM, int P, int EOS, int PREC, int MODE, int FLUX>
 hipError_t run_element(const ElemArgs& a, hipStream_t s) {
   using T = TileGeo<DIM, P>;
   const int nb = ((a.m.nex + T::TX - 1) / T::TX) * ((a.m.ney + T::TY - 1) / T::TY) *
                  ((a.m.nez + T::TZ - 1) / T::TZ);
-  hipLaunchKernelGGL((k_element<DIM, P, EOS, PREC, MODE>), dim3(nb), dim3(T::NT), 0, s, a);
+  hipLaunchKernelGGL((k_element<DIM, P, EOS, PREC, MODE, FLUX>), dim3(nb), dim3(T::NT), 0, s, a);
   return hipGetLastError();
 }
 
+template <int DIM, int P, int EOS, int PREC, int MODE>
+hipError_t by_flux(int flux, const ElemArgs& a, hipStream_t s) {
+  return flux == FLUX_HLL ? run_element<DIM, P, EOS, PREC, MODE, FLUX_HLL>(a, s)
+                          : run_element<DIM, P, EOS, PREC, MODE, FLUX_HLLC>(a, s);
+}
+
 template <int DIM, int P, int EOS, int PREC>
-hipError_t by_mode(int mode, const ElemArgs& a, hipStream_t s) {
-  return mode == MODE_RHS ? run_element<DIM, P, EOS, PREC, MODE_RHS>(a, s)
-                          : run_element<DIM, P, EOS, PREC, MODE_STAGE>(a, s);
+hipError_t by_mode(int mode, int flux, const ElemArgs& a, hipStream_t s) {
+  return mode == MODE_RHS ? by_flux<DIM, P, EOS, PREC, MODE_RHS>(flux, a, s)
+                          : by_flux<DIM, P, EOS, PREC, MODE_STAGE>(flux, a, s);
 }
 
 template <int DIM, int P, int EOS>
-hipError_t by_prec(int prec, int mode, const ElemArgs& a, hipStream_t s) {
-  return prec == PREC_FP64 ? by_mode<DIM, P, EOS, PREC_FP64>(mode, a, s)
-                           : by_mode<DIM, P, EOS, PREC_FP32>(mode, a, s);
+hipError_t by_prec(int prec, int mode, int flux, const ElemArgs& a, hipStream_t s) {
+  return prec == PREC_FP64 ? by_mode<DIM, P, EOS, PREC_FP64>(mode, flux, a, s)
+                           : by_mode<DIM, P, EOS, PREC_FP32>(mode, flux, a, s);
 }
 
 template <int DIM, int P>
-hipError_t by_eos(int eos, int prec, int mode, const ElemArgs& a, hipStream_t s) {
-  return eos == EOS_IDEAL ? by_prec<DIM, P, EOS_IDEAL>(prec, mode, a, s)
-                          : by_prec<DIM, P, EOS_TM>(prec, mode, a, s);
+hipError_t by_eos(int eos, int prec, int mode, int flux, const ElemArgs& a, hipStream_t s) {
+  return eos == EOS_IDEAL ? by_prec<DIM, P, EOS_IDEAL>(prec, mode, flux, a, s)
+                          : by_prec<DIM, P, EOS_TM>(prec, mode, flux, a, s);
 }
 
 template <int DIM, int P>
@@ -52,13 +58,13 @@ hipError_t run_enforce(double* U, const MeshArgs& m, const Tables& t, const Phys
 #define DG_CAT2(a, b) a##b
 #define DG_CAT(a, b) DG_CAT2(a, b)
 
-hipError_t DG_CAT(launch_element_dim, DG_DIM)(int p, int eos, int prec, int mode, const ElemArgs& a,
+hipError_t DG_CAT(launch_element_dim, DG_DIM)(int p, int eos, int prec, int mode, int flux, const ElemArgs& a,
                                               hipStream_t s) {
   switch (p) {
-    case 0: return by_eos<DG_DIM, 0>(eos, prec, mode, a, s);
-    case 1: return by_eos<DG_DIM, 1>(eos, prec, mode, a, s);
-    case 2: return by_eos<DG_DIM, 2>(eos, prec, mode, a, s);
-    case 3: return by_eos<DG_DIM, 3>(eos, prec, mode, a, s);
+    case 0: return by_eos<DG_DIM, 0>(eos, prec, mode, flux, a, s);
+    case 1: return by_eos<DG_DIM, 1>(eos, prec, mode, flux, a, s);
+    case 2: return by_eos<DG_DIM, 2>(eos, prec, mode, flux, a, s);
+    case 3: return by_eos<DG_DIM, 3>(eos, prec, mode, flux, a, s);
     default: return hipErrorInvalidValue;
   }
 }

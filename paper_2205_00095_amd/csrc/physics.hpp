@@ -15,6 +15,7 @@ namespace dgsrhd {
 enum { EOS_IDEAL = 0, EOS_TM = 1 };
 enum { C2P_NEWTON = 0, C2P_QUARTIC = 1, C2P_CUBIC = 2, C2P_BRENT = 3 };
 enum { C2P_OK = 0, C2P_INADMISSIBLE = 1, C2P_NOCONV = 2, C2P_BADP = 3 };
+enum { FLUX_HLL = 0, FLUX_HLLC = 1 };
 
 // Floor state written for a failed recovery: rho = 1e-10, u = 0, P = 1e-10 c^2.
 constexpr double kRhoFloor = 1e-10;
@@ -234,6 +235,72 @@ __host__ __device__ __forceinline__ void hll_flux(const double* WL, const double
     const double inv = 1.0 / (cL - cR);
 #pragma unroll
     for (int k = 0; k < NV; ++k) Fh[k] = (cL * FL[k] - cR * FR[k] + cU * (sR.U[k] - sL.U[k])) * inv;
+  }
+}
+
+// HLLC numerical flux along d (the paper's second solver, Sec. 2.4, after Mignone &
+// Bodo 2005): the HLL speeds lambda_L, lambda_R bound a fan with one contact of speed
+// lambda* and pressure p*.  With the HLL state and flux of D, S_d and tau
+// (E = tau + D c^2, F_E = F_tau + c^2 F_D), lambda* is the root inside the fan of
+//   F^hll_E lambda*^2 - c^2 (E^hll + F^hll_Sd) lambda* + c^4 S^hll_d = 0,
+// taken as 2 c^2 S^hll_d / (b + sqrt(b^2 - 4 F^hll_E S^hll_d)), b = E^hll + F^hll_Sd, and
+// p* = F^hll_Sd - lambda* F^hll_E / c^2.  The star state on side K is
+// U*_K = (lambda_K U_K - F_K + p* (0, e_d, lambda*)) / (lambda_K - lambda*) and the flux
+// F_K + lambda_K (U*_K - U_K): F_L, F*_L, F*_R or F_R by the signs of lambda_L,
+// lambda*, lambda_R.
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void hllc_flux(const double* WL, const double* WR, int d, const PhysParams& q,
+                                          double* Fh) {
+  constexpr int NV = DIM + 2;
+  StateEval<EOS, DIM> sL, sR;
+  eval_state<EOS, DIM>(WL, q, sL);
+  eval_state<EOS, DIM>(WR, q, sR);
+  double FL[NV], FR[NV];
+  flux_dir<EOS, DIM>(WL, sL, d, FL);
+  flux_dir<EOS, DIM>(WR, sR, d, FR);
+  double lmL, lpL, lmR, lpR;
+  wavespeeds<EOS, DIM>(WL, sL, d, q, lmL, lpL);
+  wavespeeds<EOS, DIM>(WR, sR, d, q, lmR, lpR);
+  const double aL = fmin(lmL, lmR), aR = fmax(lpL, lpR);
+  if (aL >= 0.0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) Fh[k] = FL[k];
+    return;
+  }
+  // HLL state and flux of the rows the contact needs (D, S_d, tau)
+  const double ih = 1.0 / (aR - aL);
+  const double ULs = comp<DIM>(sL.U + 1, d), URs = comp<DIM>(sR.U + 1, d);
+  const double FLs = comp<DIM>(FL + 1, d), FRs = comp<DIM>(FR + 1, d);
+  const double UhD = (aR * sR.U[0] - aL * sL.U[0] + FL[0] - FR[0]) * ih;
+  const double UhS = (aR * URs - aL * ULs + FLs - FRs) * ih;
+  const double UhT = (aR * sR.U[NV - 1] - aL * sL.U[NV - 1] + FL[NV - 1] - FR[NV - 1]) * ih;
+  const double FhD = (aR * FL[0] - aL * FR[0] + aL * aR * (sR.U[0] - sL.U[0])) * ih;
+  const double FhS = (aR * FLs - aL * FRs + aL * aR * (URs - ULs)) * ih;
+  const double FhT = (aR * FL[NV - 1] - aL * FR[NV - 1] + aL * aR * (sR.U[NV - 1] - sL.U[NV - 1])) * ih;
+  const double Eh = UhT + q.c2 * UhD, FEh = FhT + q.c2 * FhD;
+  const double b = Eh + FhS;
+  const double disc = fmax(b * b - 4.0 * FEh * UhS, 0.0);
+  const double lam = 2.0 * q.c2 * UhS / (b + sqrt(disc));
+  const double ps = FhS - lam * FEh * q.inv_c2;
+  const bool left = lam >= 0.0;
+  if (!left && !(aR > 0.0)) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) Fh[k] = FR[k];
+    return;
+  }
+  const double a = left ? aL : aR;
+  const double ia = 1.0 / (a - lam);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double U = left ? sL.U[k] : sR.U[k];
+    const double F = left ? FL[k] : FR[k];
+    double extra = 0.0;
+    if (k == NV - 1) extra = ps * lam;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      if (k == 1 + j && j == d) extra = ps;
+    const double Us = (a * U - F + extra) * ia;
+    Fh[k] = F + a * (Us - U);
   }
 }
 

@@ -30,6 +30,7 @@ def _desc_from_config(cfg: dict, sync: bool) -> _lib.MeshDesc:
     d.phys = 1 if cfg.get("phys", True) else 0
     d.phys_eps = float(cfg.get("phys_eps", 1e-12))
     d.sync_mode = 1 if sync else 0
+    d.flux = int(cfg.get("flux", 0))
     return d
 
 

@@ -33,6 +33,7 @@ PERIODIC, OUTFLOW = 0, 1
 EOS_IDEAL, EOS_TM = 0, 1
 C2P_NEWTON, C2P_QUARTIC, C2P_CUBIC, C2P_BRENT = 0, 1, 2, 3
 FP64, FP32_CONTRACT = 0, 1
+FLUX_HLL, FLUX_HLLC = 0, 1
 
 
 def cfl_dt(cfg: dict) -> float:

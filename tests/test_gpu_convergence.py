@@ -42,3 +42,37 @@ def test_sound_wave_converges_on_gpu(dim, p, Ns, lo):
     rates = [math.log2(e[i] / e[i + 1]) for i in range(len(e) - 1)]
     print(f"dim {dim} p {p}: errors {e} rates {rates}", flush=True)
     assert rates[-1] > lo, (e, rates)
+
+
+def _gpu_wave1d_period_error(N, p, order):
+    """L1 error of D after one period (t = 2: the density wave moves at v = 0.5 on a
+    unit periodic domain and returns onto its initial profile; exact translated
+    solution of the SRHD contact wave)."""
+    from paper_2205_00095_amd.solver import Solver
+    cfg = wl.make_config("wave1d", n_elem=(N, 1, 1), p=p)
+    s = Solver(cfg)
+    src = torch.from_numpy(wl.pack_primitives(*wl.initial_primitives(cfg))).cuda()
+    U0 = s.set_state(src)
+    U = U0.clone()
+    T = 2.0
+    n = int(math.ceil(T / cfg["dt"]))
+    s.run(U, T / n, n, order=order)
+    w = torch.tensor(basis.tables(p)["w"])
+    err = float(((U[0] - U0[0]).abs().cpu() * w).sum()) / (2 * N)
+    d = s.diagnostics()
+    assert d["c2p_fail"] == 0 and d["flagged"] == 0
+    s.close()
+    return err
+
+
+@pytest.mark.parametrize("p,order,Ns,lo", [(1, 2, (32, 64, 128), 1.9), (2, 3, (16, 32, 64), 2.8),
+                                          (3, 3, (8, 16, 32), 2.8)])
+def test_density_wave_one_period_on_gpu(p, order, Ns, lo):
+    """After a full period the solution is back on the initial data up to the scheme's
+    error, which falls at order >= p + 1 (at least 3 with SSP-RK3, whose time error
+    caps p = 3); checks the phase over a long run (thousands of steps)."""
+    e = [_gpu_wave1d_period_error(N, p, order) for N in Ns]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(len(e) - 1)]
+    print(f"wave1d p {p}: errors {e} rates {rates}", flush=True)
+    assert rates[-1] > lo, (e, rates)
+    assert e[-1] < 1e-4, e
