@@ -23,6 +23,7 @@ struct dg_ctx {
   size_t adj_doubles = 0;
   dgsrhd::Counters* cnt = nullptr;
   dgsrhd::Counters last{};           // counter snapshot for sync-mode error reporting
+  int flip = 0;                      // tile direction of the last element launch
   std::string err;
 };
 

@@ -145,8 +145,12 @@ void gl_tables(int p, int dim, Tables& t) {
   }
 }
 
-hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a) {
+hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a0) {
   const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos, prec = c->desc.precision, fl = c->desc.flux;
+  // consecutive launches walk the tiles in opposite directions (cache reuse)
+  ElemArgs a = a0;
+  c->flip ^= 1;
+  a.rev = c->flip;
   if (dim == 1) return launch_element_dim1(p, eos, prec, mode, fl, a, c->stream);
   if (dim == 2) return launch_element_dim2(p, eos, prec, mode, fl, a, c->stream);
   return launch_element_dim3(p, eos, prec, mode, fl, a, c->stream);

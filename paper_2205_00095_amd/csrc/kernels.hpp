@@ -81,6 +81,7 @@ struct ElemArgs {
   PhysParams q;
   Counters* cnt;
   unsigned* opflag;   // set to 1 when the operator changed an element (taped stages), or null
+  int rev;            // walk each XCD's tile range backwards (see xcd_tile)
 };
 
 // Wave-aggregated event counting: one atomic per wave and counter (the counters are
@@ -525,11 +526,15 @@ struct TileFacePoint {
 // (hardware block b runs on XCD b % 8), so hardware block b is mapped to logical
 // tile start(x) + b / 8, where XCD x owns the contiguous range of nb/8 (+1 for the
 // first nb % 8 XCDs) tiles starting at start(x).  Neighbouring tiles, which read
-// each other's halo primitives, then share one XCD's L2.  A bijection for any nb.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
+// each other's halo primitives, then share one XCD's L2.  With rev the range is
+// walked backwards: consecutive stage launches alternate direction, so a stage
+// starts on the tiles whose outputs the previous one wrote last, still in that
+// XCD's L2.  A bijection for any nb.
+__device__ __forceinline__ int xcd_tile(int b, int nb, int rev = 0) {
   const int q = nb >> 3, r = nb & 7;
   const int x = b & 7, k = b >> 3;
-  return x * q + min(x, r) + k;
+  const int cnt = q + (x < r ? 1 : 0);
+  return x * q + min(x, r) + (rev ? cnt - 1 - k : k);
 }
 
 // Primitive trace at one point of an element face normal to d, interpolated along the
@@ -612,7 +617,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   const int el = tid / NPE, node = tid % NPE;
   // tile origin
   const int ntx = (m.nex + TX - 1) / TX, nty = (m.ney + TY - 1) / TY, ntz = (m.nez + TZ - 1) / TZ;
-  const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
+  const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz, a.rev);
   const int o[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * TZ};
   const int lc[3] = {el % TX, (el / TX) % TY, el / (TX * TY)};
   const bool act = (o[0] + lc[0] < m.nex) && (o[1] + lc[1] < m.ney) && (o[2] + lc[2] < m.nez);
