@@ -125,3 +125,17 @@ def test_adjoint_refuses_hllc():
         s.rhs_vjp(Ud, torch.ones_like(Ud))
     assert ei.value.code == _lib.DG_EINVAL
     assert "HLL flux only" in str(ei.value)
+
+
+def test_hllc_fullsize_rhs():
+    """The 256x256 p=3 Taub-Matthews Kelvin-Helmholtz mesh, every output against the
+    (vectorised) oracle, in the launch configuration of the benchmark."""
+    cfg = _cfg("kh_tm", {})
+    print(f"case hllc fullsize {cfg['n_elem']}", flush=True)
+    st, U = oracle_state(cfg)
+    R_ref = odg.rhs(U, st)
+    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    R = _solver(cfg, sync=False).rhs(U.cuda()).cpu()
+    err = rel_err_per_var(R, R_ref)
+    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
+    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
