@@ -73,8 +73,7 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * the faces (Sec. 2.4): DG_FLUX_HLL (0, the default when the field is zeroed) or
  * DG_FLUX_HLLC, the HLLC solver of Mignone & Bodo (2005) with one contact wave
  * inside the HLL fan (exact on isolated contacts, including tangential-velocity
- * jumps); the adjoint entry points (the taped steps and every *_vjp* call)
- * support HLL only and return DG_EINVAL for HLLC. */
+ * jumps); the adjoint entry points differentiate whichever flux is selected. */
 typedef struct {
   int dim, p;
   int n_elem[3];

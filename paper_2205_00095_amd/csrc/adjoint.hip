@@ -72,9 +72,10 @@ hipError_t clear_tape_flags(dg_ctx* c, double* tapes, int nsteps) {
 
 hipError_t L_vjp(dg_ctx* c, int mode, const VjpArgs& a) {
   const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos;
-  if (dim == 1) return launch_vjp_dim1(p, eos, mode, a, c->stream);
-  if (dim == 2) return launch_vjp_dim2(p, eos, mode, a, c->stream);
-  return launch_vjp_dim3(p, eos, mode, a, c->stream);
+  const int fl = c->desc.flux;
+  if (dim == 1) return launch_vjp_dim1(p, eos, mode, fl, a, c->stream);
+  if (dim == 2) return launch_vjp_dim2(p, eos, mode, fl, a, c->stream);
+  return launch_vjp_dim3(p, eos, mode, fl, a, c->stream);
 }
 
 hipError_t L_enforce_vjp(dg_ctx* c, const double* Pst, const double* lin, double* lout, const unsigned* flag) {
@@ -184,12 +185,6 @@ int step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_ne
   return hipcheck(c, L_vjp(c, VJP_STAGE, a), what);
 }
 
-// The reverse kernels differentiate the HLL flux only.
-int hll_only(dg_ctx* c, const char* what) {
-  if (c->desc.flux != DG_FLUX_HLL) return fail(c, DG_EINVAL, "%s: the adjoint supports the HLL flux only", what);
-  return DG_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -198,7 +193,6 @@ int dg_rhs_vjp(dg_ctx* c, const double* U, const double* lamR, double* lamU) {
   if (!c) return DG_EINVAL;
   if (!U || !lamR || !lamU) return fail(c, DG_EINVAL, "dg_rhs_vjp: null pointer");
   if (lamU == lamR || lamU == U) return fail(c, DG_EINVAL, "dg_rhs_vjp: output aliases an input");
-  if (int rf = hll_only(c, "dg_rhs_vjp")) return rf;
   int r = hipcheck(c, L_con2prim(c, U, c->Wa), "dg_rhs_vjp/con2prim");
   if (r) return r;
   VjpArgs a = vjp_args(c);
@@ -214,7 +208,6 @@ size_t dg_tape_size(const dg_ctx* c) { return c ? tape_doubles(c) : 0; }
 int dg_ssprk3_step_tape(dg_ctx* c, double* U, double dt, double* tape) {
   if (!c) return DG_EINVAL;
   if (!U || !tape) return fail(c, DG_EINVAL, "dg_ssprk3_step_tape: null pointer");
-  if (int rf = hll_only(c, "dg_ssprk3_step_tape")) return rf;
   int r = hipcheck(c, clear_tape_flags(c, tape, 1), "dg_ssprk3_step_tape");
   if (r) return r;
   r = step_tape(c, U, dt, tape, "dg_ssprk3_step_tape");
@@ -225,7 +218,6 @@ int dg_ssprk3_step_tape(dg_ctx* c, double* U, double dt, double* tape) {
 int dg_ssprk3_step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_next, double* lam_n) {
   if (!c) return DG_EINVAL;
   if (!tape || !lam_next || !lam_n) return fail(c, DG_EINVAL, "dg_ssprk3_step_vjp_tape: null pointer");
-  if (int rf = hll_only(c, "dg_ssprk3_step_vjp_tape")) return rf;
   int r = ensure_adj(c);
   if (r) return r;
   if ((r = step_vjp_tape(c, tape, dt, lam_next, lam_n, "dg_ssprk3_step_vjp_tape"))) return r;
@@ -236,7 +228,6 @@ int dg_ssprk3_run_tape(dg_ctx* c, double* U, double dt, int nsteps, double* tape
   if (!c) return DG_EINVAL;
   if (!U || !tapes) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: null pointer");
   if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: nsteps < 0");
-  if (int rf = hll_only(c, "dg_ssprk3_run_tape")) return rf;
   const size_t T = tape_doubles(c);
   int r0 = hipcheck(c, clear_tape_flags(c, tapes, nsteps), "dg_ssprk3_run_tape");
   if (r0) return r0;
@@ -252,7 +243,6 @@ int dg_ssprk3_run_vjp_tape(dg_ctx* c, const double* tapes, double dt, int nsteps
   if (!c) return DG_EINVAL;
   if (!tapes || !lam) return fail(c, DG_EINVAL, "dg_ssprk3_run_vjp_tape: null pointer");
   if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_vjp_tape: nsteps < 0");
-  if (int rf = hll_only(c, "dg_ssprk3_run_vjp_tape")) return rf;
   int r = ensure_adj(c);
   if (r) return r;
   const size_t T = tape_doubles(c);
@@ -267,7 +257,6 @@ int dg_ssprk3_run_vjp_tape(dg_ctx* c, const double* tapes, double dt, int nsteps
 int dg_ssprk3_step_vjp(dg_ctx* c, const double* Un, double dt, const double* lam_next, double* lam_n) {
   if (!c) return DG_EINVAL;
   if (!Un || !lam_next || !lam_n) return fail(c, DG_EINVAL, "dg_ssprk3_step_vjp: null pointer");
-  if (int rf = hll_only(c, "dg_ssprk3_step_vjp")) return rf;
   int r = ensure_adj(c);
   if (r) return r;
   double* Ut = adj_state(c, A_UTMP);

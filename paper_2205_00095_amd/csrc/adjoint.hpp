@@ -267,7 +267,7 @@ __device__ __forceinline__ bool trace_lam_glb(const double* srcW, const double* 
 template <int DIM, int P, int EOS>
 constexpr int vjp_min_waves() { return P == 0 ? 1 : (DIM == 2 && EOS == EOS_IDEAL) ? 3 : 2; }
 
-template <int DIM, int P, int EOS, int MODE>
+template <int DIM, int P, int EOS, int MODE, int FLUX>
 __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>())) void k_rhs_vjp(VjpArgs a) {
   using T = TileGeo<DIM, P>;
   constexpr int N1 = T::N1, NPE = T::NPE, NV = T::NV, NT = T::NT, EPB = T::EPB;
@@ -376,7 +376,10 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
       double lamWA[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) lamWA[v] = 0.0;
-      hll_flux_rev<EOS, DIM>(WA, WA, d, q, lamFh, lamWA, lamWA, true, true);
+      if constexpr (FLUX == FLUX_HLLC)
+        hllc_flux_rev<EOS, DIM>(WA, WA, d, q, lamFh, lamWA, lamWA, true, true);
+      else
+        hll_flux_rev<EOS, DIM>(WA, WA, d, q, lamFh, lamWA, lamWA, true, true);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         lamWL[v] = a_left ? lamWA[v] : 0.0;
@@ -389,7 +392,10 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
         WL[v] = a_left ? WA[v] : WB[v];
         WR[v] = a_left ? WB[v] : WA[v];
       }
-      hll_flux_rev<EOS, DIM>(WL, WR, d, q, lamFh, lamWL, lamWR, left_local, right_local);
+      if constexpr (FLUX == FLUX_HLLC)
+        hllc_flux_rev<EOS, DIM>(WL, WR, d, q, lamFh, lamWL, lamWR, left_local, right_local);
+      else
+        hll_flux_rev<EOS, DIM>(WL, WR, d, q, lamFh, lamWL, lamWR, left_local, right_local);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

@@ -6,7 +6,8 @@
 namespace dgsrhd {
 
 #define DG_DECLARE_LAUNCHERS(D)                                                                          \
-  hipError_t launch_element_dim##D(int p, int eos, int prec, int mode, int flux, const ElemArgs& a, hipStream_t s); \
+  hipError_t launch_element_dim##D(int p, int eos, int prec, int mode, int flux, const ElemArgs& a,       \
+                                   hipStream_t s);                                                        \
   hipError_t launch_enforce_dim##D(int p, double* U, const MeshArgs& m, const Tables& t,                  \
                                    const PhysParams& q, Counters* c, hipStream_t s);                      \
   hipError_t launch_con2prim_dim##D(int eos, const double* U, double* W, long long ntot, int npe,         \

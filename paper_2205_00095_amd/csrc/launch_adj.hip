@@ -10,22 +10,27 @@ namespace dgsrhd {
 
 namespace {
 
-template <int DIM, int P, int EOS, int MODE>
+template <int DIM, int P, int EOS, int MODE, int FLUX>
 hipError_t run_vjp(const VjpArgs& a, hipStream_t s) {
   using T = TileGeo<DIM, P>;
   const int nb = ((a.m.nex + T::TX - 1) / T::TX) * ((a.m.ney + T::TY - 1) / T::TY) *
                  ((a.m.nez + T::TZ - 1) / T::TZ);
-  hipLaunchKernelGGL((k_rhs_vjp<DIM, P, EOS, MODE>), dim3(nb), dim3(T::NT), 0, s, a);
+  hipLaunchKernelGGL((k_rhs_vjp<DIM, P, EOS, MODE, FLUX>), dim3(nb), dim3(T::NT), 0, s, a);
   return hipGetLastError();
 }
 
+template <int DIM, int P, int EOS, int MODE>
+hipError_t vjp_by_flux(int flux, const VjpArgs& a, hipStream_t s) {
+  return flux == FLUX_HLL ? run_vjp<DIM, P, EOS, MODE, FLUX_HLL>(a, s) : run_vjp<DIM, P, EOS, MODE, FLUX_HLLC>(a, s);
+}
+
 template <int DIM, int P>
-hipError_t vjp_by(int eos, int mode, const VjpArgs& a, hipStream_t s) {
+hipError_t vjp_by(int eos, int mode, int flux, const VjpArgs& a, hipStream_t s) {
   if (eos == EOS_IDEAL)
-    return mode == VJP_PLAIN ? run_vjp<DIM, P, EOS_IDEAL, VJP_PLAIN>(a, s)
-                             : run_vjp<DIM, P, EOS_IDEAL, VJP_STAGE>(a, s);
-  return mode == VJP_PLAIN ? run_vjp<DIM, P, EOS_TM, VJP_PLAIN>(a, s)
-                           : run_vjp<DIM, P, EOS_TM, VJP_STAGE>(a, s);
+    return mode == VJP_PLAIN ? vjp_by_flux<DIM, P, EOS_IDEAL, VJP_PLAIN>(flux, a, s)
+                             : vjp_by_flux<DIM, P, EOS_IDEAL, VJP_STAGE>(flux, a, s);
+  return mode == VJP_PLAIN ? vjp_by_flux<DIM, P, EOS_TM, VJP_PLAIN>(flux, a, s)
+                           : vjp_by_flux<DIM, P, EOS_TM, VJP_STAGE>(flux, a, s);
 }
 
 template <int DIM, int P>
@@ -42,12 +47,12 @@ hipError_t run_enforce_vjp(const double* Pst, const double* lin, double* lout, c
 #define DG_CAT2(a, b) a##b
 #define DG_CAT(a, b) DG_CAT2(a, b)
 
-hipError_t DG_CAT(launch_vjp_dim, DG_DIM)(int p, int eos, int mode, const VjpArgs& a, hipStream_t s) {
+hipError_t DG_CAT(launch_vjp_dim, DG_DIM)(int p, int eos, int mode, int flux, const VjpArgs& a, hipStream_t s) {
   switch (p) {
-    case 0: return vjp_by<DG_DIM, 0>(eos, mode, a, s);
-    case 1: return vjp_by<DG_DIM, 1>(eos, mode, a, s);
-    case 2: return vjp_by<DG_DIM, 2>(eos, mode, a, s);
-    case 3: return vjp_by<DG_DIM, 3>(eos, mode, a, s);
+    case 0: return vjp_by<DG_DIM, 0>(eos, mode, flux, a, s);
+    case 1: return vjp_by<DG_DIM, 1>(eos, mode, flux, a, s);
+    case 2: return vjp_by<DG_DIM, 2>(eos, mode, flux, a, s);
+    case 3: return vjp_by<DG_DIM, 3>(eos, mode, flux, a, s);
     default: return hipErrorInvalidValue;
   }
 }

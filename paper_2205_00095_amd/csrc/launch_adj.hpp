@@ -5,7 +5,7 @@
 namespace dgsrhd {
 
 #define DG_DECLARE_ADJ_LAUNCHERS(D)                                                                             \
-  hipError_t launch_vjp_dim##D(int p, int eos, int mode, const VjpArgs& a, hipStream_t s);                      \
+  hipError_t launch_vjp_dim##D(int p, int eos, int mode, int flux, const VjpArgs& a, hipStream_t s);           \
   hipError_t launch_enforce_vjp_dim##D(int p, const double* Pst, const double* lin, double* lout,              \
                                        const unsigned* flag, const MeshArgs& m, const Tables& t,                \
                                        const PhysParams& q, hipStream_t s);                                     \

@@ -256,6 +256,162 @@ __host__ __device__ __forceinline__ void hll_flux_rev(const double* WL, const do
   }
 }
 
+// Adjoint of hllc_flux(WL, WR, d): accumulates into lam_WL and lam_WR.  The forward
+// branch is retaken; in the star branch the reverse runs through the star state of
+// the upwind side, the contact speed and pressure, the HLL state and flux rows they
+// use, and the outer speeds.
+template <int EOS, int DIM>
+__host__ __device__ __forceinline__ void hllc_flux_rev(const double* WL, const double* WR, int d,
+                                              const PhysParams& q, const double* lam_Fh, double* lam_WL,
+                                              double* lam_WR, bool need_L = true, bool need_R = true) {
+  constexpr int NV = DIM + 2;
+  StateEval<EOS, DIM> sL, sR;
+  eval_state<EOS, DIM>(WL, q, sL);
+  eval_state<EOS, DIM>(WR, q, sR);
+  double FL[NV], FR[NV];
+  flux_dir<EOS, DIM>(WL, sL, d, FL);
+  flux_dir<EOS, DIM>(WR, sR, d, FR);
+  double lmL, lpL, lmR, lpR;
+  wavespeeds<EOS, DIM>(WL, sL, d, q, lmL, lpL);
+  wavespeeds<EOS, DIM>(WR, sR, d, q, lmR, lpR);
+  const double aL = fmin(lmL, lmR), aR = fmax(lpL, lpR);
+  double lam_FL[NV], lam_FR[NV], lam_UL[NV], lam_UR[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) lam_FL[k] = lam_FR[k] = lam_UL[k] = lam_UR[k] = 0.0;
+  double lam_lmL = 0.0, lam_lpL = 0.0, lam_lmR = 0.0, lam_lpR = 0.0;
+  bool speeds = false;
+  if (aL >= 0.0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lam_FL[k] = lam_Fh[k];
+  } else {
+    // forward: HLL rows, contact speed and pressure
+    const double ih = 1.0 / (aR - aL);
+    const double ULs = comp<DIM>(sL.U + 1, d), URs = comp<DIM>(sR.U + 1, d);
+    const double FLs = comp<DIM>(FL + 1, d), FRs = comp<DIM>(FR + 1, d);
+    const double UhD = (aR * sR.U[0] - aL * sL.U[0] + FL[0] - FR[0]) * ih;
+    const double UhS = (aR * URs - aL * ULs + FLs - FRs) * ih;
+    const double UhT = (aR * sR.U[NV - 1] - aL * sL.U[NV - 1] + FL[NV - 1] - FR[NV - 1]) * ih;
+    const double FhD = (aR * FL[0] - aL * FR[0] + aL * aR * (sR.U[0] - sL.U[0])) * ih;
+    const double FhS = (aR * FLs - aL * FRs + aL * aR * (URs - ULs)) * ih;
+    const double FhT = (aR * FL[NV - 1] - aL * FR[NV - 1] + aL * aR * (sR.U[NV - 1] - sL.U[NV - 1])) * ih;
+    const double Eh = UhT + q.c2 * UhD, FEh = FhT + q.c2 * FhD;
+    const double b = Eh + FhS;
+    const double disc0 = b * b - 4.0 * FEh * UhS;
+    const double disc = fmax(disc0, 0.0);
+    const double sd = sqrt(disc);
+    const double den = b + sd;
+    const double lam = 2.0 * q.c2 * UhS / den;
+    const double ps = FhS - lam * FEh * q.inv_c2;
+    const bool left = lam >= 0.0;
+    if (!left && !(aR > 0.0)) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) lam_FR[k] = lam_Fh[k];
+    } else {
+      speeds = true;
+      const double a = left ? aL : aR;
+      const double ia = 1.0 / (a - lam);
+      double lam_a = 0.0, lam_ia = 0.0, lam_ps = 0.0, lam_lam = 0.0;
+      double lam_Us_side[NV], lam_Fs_side[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const double U = left ? sL.U[k] : sR.U[k];
+        const double F = left ? FL[k] : FR[k];
+        double extra = 0.0;
+        if (k == NV - 1) extra = ps * lam;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j)
+          if (k == 1 + j && j == d) extra = ps;
+        const double num = a * U - F + extra;
+        const double Us = num * ia;
+        // Fout = F + a (Us - U)
+        const double lf = lam_Fh[k];
+        double lF = lf, lU = -lf * a;
+        lam_a += lf * (Us - U);
+        const double lam_num = lf * a * ia;
+        lam_ia += lf * a * num;
+        lam_a += lam_num * U;
+        lU += lam_num * a;
+        lF -= lam_num;
+        if (k == NV - 1) {
+          lam_ps += lam_num * lam;
+          lam_lam += lam_num * ps;
+        }
+#pragma unroll
+        for (int j = 0; j < DIM; ++j)
+          if (k == 1 + j && j == d) lam_ps += lam_num;
+        lam_Us_side[k] = lU;
+        lam_Fs_side[k] = lF;
+      }
+      // ia = 1 / (a - lam)
+      const double lam_diff = -lam_ia * ia * ia;
+      lam_a += lam_diff;
+      lam_lam -= lam_diff;
+      // ps = FhS - lam FEh / c^2
+      double lam_FhS = lam_ps;
+      lam_lam += -lam_ps * FEh * q.inv_c2;
+      double lam_FEh = -lam_ps * lam * q.inv_c2;
+      // lam = 2 c^2 UhS / den,  den = b + sqrt(disc)
+      double lam_UhS = lam_lam * 2.0 * q.c2 / den;
+      const double lam_den = -lam_lam * lam / den;
+      double lam_b = lam_den;
+      if (disc0 > 0.0) {
+        const double lam_disc = lam_den * 0.5 / sd;
+        lam_b += 2.0 * b * lam_disc;
+        lam_FEh += -4.0 * UhS * lam_disc;
+        lam_UhS += -4.0 * FEh * lam_disc;
+      }
+      // b = Eh + FhS; Eh = UhT + c^2 UhD; FEh = FhT + c^2 FhD
+      lam_FhS += lam_b;
+      const double lam_UhT = lam_b, lam_UhD = q.c2 * lam_b;
+      const double lam_FhT = lam_FEh, lam_FhD = q.c2 * lam_FEh;
+      // HLL rows: Uh = (aR UR - aL UL + FL - FR) ih, Fh = (aR FL - aL FR + aL aR (UR - UL)) ih
+      double lam_aL = 0.0, lam_aR = 0.0;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        double lUh = 0.0, lFh = 0.0;
+        if (k == 0) { lUh = lam_UhD; lFh = lam_FhD; }
+        if (k == NV - 1) { lUh = lam_UhT; lFh = lam_FhT; }
+#pragma unroll
+        for (int j = 0; j < DIM; ++j)
+          if (k == 1 + j && j == d) { lUh = lam_UhS; lFh = lam_FhS; }
+        const double dU = sR.U[k] - sL.U[k];
+        const double Uh = (aR * sR.U[k] - aL * sL.U[k] + FL[k] - FR[k]) * ih;
+        const double Fh = (aR * FL[k] - aL * FR[k] + aL * aR * dU) * ih;
+        lam_UR[k] += lUh * aR * ih + lFh * aL * aR * ih;
+        lam_UL[k] += -lUh * aL * ih - lFh * aL * aR * ih;
+        lam_FL[k] += lUh * ih + lFh * aR * ih;
+        lam_FR[k] += -lUh * ih - lFh * aL * ih;
+        lam_aR += lUh * (sR.U[k] - Uh) * ih + lFh * (FL[k] + aL * dU - Fh) * ih;
+        lam_aL += lUh * (Uh - sL.U[k]) * ih + lFh * (-FR[k] + aR * dU + Fh) * ih;
+      }
+      // the upwind side's own U and F, and its speed
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        if (left) {
+          lam_UL[k] += lam_Us_side[k];
+          lam_FL[k] += lam_Fs_side[k];
+        } else {
+          lam_UR[k] += lam_Us_side[k];
+          lam_FR[k] += lam_Fs_side[k];
+        }
+      }
+      if (left) lam_aL += lam_a; else lam_aR += lam_a;
+      if (lmL <= lmR) lam_lmL = lam_aL; else lam_lmR = lam_aL;
+      if (lpL >= lpR) lam_lpL = lam_aR; else lam_lpR = lam_aR;
+    }
+  }
+  if (need_L) {
+    SpeedParts p;
+    speed_parts<EOS, DIM>(WL, sL, d, q, p);
+    state_flux_speed_rev<EOS, DIM>(WL, sL, p, d, q, lam_UL, lam_FL, lam_lmL, lam_lpL, speeds, lam_WL);
+  }
+  if (need_R) {
+    SpeedParts p;
+    speed_parts<EOS, DIM>(WR, sR, d, q, p);
+    state_flux_speed_rev<EOS, DIM>(WR, sR, p, d, q, lam_UR, lam_FR, lam_lmR, lam_lpR, speeds, lam_WR);
+  }
+}
+
 // J[r][c] = dU_r / dW_c at the primitive state W (Eq. primitive_to_conserved).
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void prim_jacobian(const double* W, const PhysParams& q, double J[DIM + 2][DIM + 2]) {

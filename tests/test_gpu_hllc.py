@@ -1,14 +1,13 @@
 """The HLLC flux on the GPU (Sec. 2.4, the paper's second solver): parity of the RHS and
 of SSP-RK steps with the FP64 oracle, the FP32-contraction form against the FP64 path,
 an isolated contact that the GPU operator keeps exactly steady (HLL does not), and the
-adjoint entry points refusing HLLC."""
+hand-written adjoint of the HLLC flux against the oracle's reverse mode."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import dg as odg
 from oracle import timestep as ots
-from paper_2205_00095_amd import _lib
 from paper_2205_00095_amd import workloads as wl
 
 from ._util import oracle_state, parity_tol, rel_err_per_var
@@ -116,15 +115,55 @@ def test_hllc_keeps_an_isolated_contact_steady(p):
     assert out[wl.FLUX_HLL] > 1e-3
 
 
-def test_adjoint_refuses_hllc():
-    cfg = _cfg("kh_ideal", {"n_elem": (6, 5, 1)})
+def _lam(shape, seed):
+    g = torch.Generator().manual_seed(seed)
+    return torch.randn(shape, generator=g, dtype=torch.float64)
+
+
+def _perturbed_sensitivity(fn, U):
+    from ._util import perturbed
+    return rel_err_per_var(fn(perturbed(U)), fn(U))
+
+
+VJP_CASES = [("kh_ideal", {"n_elem": (6, 5, 1), "init": "kh"}), ("kh_tm", {"n_elem": (5, 4, 1)}),
+             ("wave1d", {"n_elem": (20, 1, 1)}), ("random3d", {"n_elem": (3, 2, 2), "p": 1}),
+             ("kh_ideal", {"n_elem": (5, 4, 1), "p": 3, "init": "kh"})]
+
+
+@pytest.mark.parametrize("kind,over", VJP_CASES)
+def test_hllc_rhs_vjp_matches_oracle_autograd(kind, over):
+    """dg_rhs_vjp with HLLC against the oracle's reverse mode (autograd through its HLLC)."""
+    cfg = _cfg(kind, over)
+    print(f"case hllc rhs_vjp {kind} {over}", flush=True)
     st, U = oracle_state(cfg)
-    s = _solver(cfg)
-    Ud = U.cuda()
-    with pytest.raises(_lib.DGError) as ei:
-        s.rhs_vjp(Ud, torch.ones_like(Ud))
-    assert ei.value.code == _lib.DG_EINVAL
-    assert "HLL flux only" in str(ei.value)
+    lamR = _lam(U.shape, 7)
+
+    def ref_of(V):
+        Vr = V.clone().requires_grad_(True)
+        return torch.autograd.grad(odg.rhs(Vr, st), Vr, lamR)[0]
+
+    ref = ref_of(U)
+    sens = _perturbed_sensitivity(ref_of, U)
+    assert float(sens.max()) < 1e-10, f"test data sits on a derivative kink: {sens.tolist()}"
+    got = _solver(cfg).rhs_vjp(U.cuda(), lamR.cuda()).cpu()
+    err = rel_err_per_var(got, ref)
+    print(f"err {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9, err.tolist()
+
+
+@pytest.mark.parametrize("kind,over", [("kh_ideal", {"n_elem": (6, 5, 1), "init": "kh"}),
+                                       ("kh_tm", {"n_elem": (4, 4, 1)})])
+def test_hllc_step_vjp_matches_oracle_autograd(kind, over):
+    cfg = _cfg(kind, over)
+    print(f"case hllc step_vjp {kind} {over}", flush=True)
+    st, U = oracle_state(cfg)
+    lam = _lam(U.shape, 11)
+    Ur = U.clone().requires_grad_(True)
+    (ref,) = torch.autograd.grad(ots.step(Ur, cfg["dt"], st), Ur, lam)
+    got = _solver(cfg).step_vjp(U.cuda(), cfg["dt"], lam.cuda()).cpu()
+    err = rel_err_per_var(got, ref)
+    print(f"err {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9, err.tolist()
 
 
 def test_hllc_fullsize_rhs():
