@@ -76,3 +76,23 @@ def test_density_wave_one_period_on_gpu(p, order, Ns, lo):
     print(f"wave1d p {p}: errors {e} rates {rates}", flush=True)
     assert rates[-1] > lo, (e, rates)
     assert e[-1] < 1e-4, e
+
+
+def test_sound_wave_order_matches_the_papers_table():
+    """3D non-grid-aligned acoustic wave at rest, p = 2 with SSP-RK3: the order of the
+    error of D is within 0.3 of the order the paper prints for the acoustic (- and +)
+    cases (Sec. 4, linear waves; tests/golden/linear_wave_orders_3d_p2.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "linear_wave_orders_3d_p2.txt")
+    table = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                q, *vals = line.split()
+                table[q] = vals
+    paper = float(table["D"][0])
+    assert paper == float(table["D"][4])  # the two acoustic cases agree
+    e = [_gpu_period_error(N, 2, 3) for N in (4, 8, 16)]
+    rate = math.log2(e[1] / e[2])
+    print(f"3D p=2 acoustic: errors {e} order {rate:.3f} (paper {paper})", flush=True)
+    assert abs(rate - paper) <= 0.3, (rate, paper)
