@@ -13,7 +13,8 @@ Steps, in the order of Sec. 2.3:
         W^+ = sum_a l_a(+1) W_a,   W^- = sum_a l_a(-1) W_a  along d.
     Reading: a trace with rho <= 0 or P <= 0 is replaced by the primitive
     state of the node nearest to that face on the same line (counted);
- 4. exterior states: periodic neighbour, or outflow (exterior = interior);
+ 4. exterior states: periodic neighbour, outflow (exterior = interior), or a
+    reflecting wall (the interior trace with its normal velocity negated);
  5. HLL (or HLLC) numerical flux at every face point, Eq. (quad-surface-flux);
  6. lift with the inverse mass:
         S_i = -sum_d (2/dx_d)(1/w_{i_d}) [l_{i_d}(+1) Fhat^+ - l_{i_d}(-1) Fhat^-];
@@ -22,8 +23,10 @@ Steps, in the order of Sec. 2.3:
 Pinned by tests/test_oracle_dg.py: zero RHS for a uniform state, exact
 discrete conservation on a periodic mesh, mirror and axis-swap symmetries, a
 2D field constant in y equals the 1D operator, p = 0 equals a first-order HLL
-finite-volume update written independently, and (test_oracle_convergence.py)
-order ~p+1 on the exact translated density wave.
+finite-volume update written independently, a reflecting wall equals a periodic
+mesh of twice the size holding the mirrored state, a closed box conserves mass
+and energy, and (test_oracle_timestep.py) order ~p+1 on the exact translated
+density wave.
 """
 from __future__ import annotations
 
@@ -31,7 +34,7 @@ import torch
 
 from . import basis
 from .con2prim import con2prim
-from .setup import PERIODIC
+from .setup import PERIODIC, REFLECT
 from .srhd import face_flux, flux
 
 
@@ -76,10 +79,20 @@ def face_states(Wm, Wp, d, st):
     if st.bc[d] == PERIODIC:
         WL = torch.cat([last_p, Wp], ea)
         WR = torch.cat([Wm, first_m], ea)
+    elif st.bc[d] == REFLECT:  # a wall: the interior trace with its normal velocity negated
+        WL = torch.cat([_mirrored(first_m, d), Wp], ea)
+        WR = torch.cat([Wm, _mirrored(last_p, d)], ea)
     else:  # outflow: exterior state equals the interior trace
         WL = torch.cat([first_m, Wp], ea)
         WR = torch.cat([Wm, last_p], ea)
     return WL, WR
+
+
+def _mirrored(W, d):
+    """Primitive states reflected across a plane normal to d: u_d -> -u_d."""
+    M = W.clone()
+    M[1 + d] = -M[1 + d]
+    return M
 
 
 def surface_term(W, st, stats=None):

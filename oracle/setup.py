@@ -3,7 +3,7 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
-PERIODIC, OUTFLOW = 0, 1
+PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 IDEAL, TM = 0, 1
 NEWTON, QUARTIC, CUBIC, BRENT = 0, 1, 2, 3
 HLL, HLLC = 0, 1

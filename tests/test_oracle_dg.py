@@ -159,3 +159,44 @@ def test_hllc_rhs_uniform_zero_and_conservative(dim, p, eos):
     tot = wR.sum((1, 2, 3, 4, 5, 6))
     scale = wR.abs().sum((1, 2, 3, 4, 5, 6))
     assert float((tot.abs() / scale).max()) < 1e-13
+
+
+def _mirror_x(U):
+    """The state reflected across x = const: element and node order along x reversed,
+    S_x negated (D, S_y, S_z and tau are even)."""
+    M = U.flip(3).flip(6).clone()
+    M[1] = -M[1]
+    return M
+
+
+@pytest.mark.parametrize("dim,p,eos,flux", [(1, 2, IDEAL, 0), (1, 3, TM, 1), (2, 1, TM, 0), (2, 2, IDEAL, 1)])
+def test_reflecting_wall_equals_mirrored_periodic_mesh(dim, p, eos, flux):
+    """Walls at both ends in x give the RHS of a periodic mesh of twice the length that
+    holds the state followed by its mirror image (the image supplies the exterior
+    state at each wall)."""
+    from oracle.setup import REFLECT
+    ny = 3 if dim > 1 else 1
+    st = Setup(dim=dim, p=p, n_elem=(5, ny, 1), eos=eos, bc=(REFLECT, PERIODIC, PERIODIC), flux=flux)
+    st2 = Setup(dim=dim, p=p, n_elem=(10, ny, 1), lo=(0.0, 0.0, 0.0), hi=(2.0, 1.0, 1.0), eos=eos,
+                bc=(PERIODIC, PERIODIC, PERIODIC), flux=flux)
+    U = _random_state(st, np.random.default_rng(60 + dim + p), gmax=2.0)
+    U2 = torch.cat([U, _mirror_x(U)], 3)
+    R = dg.rhs(U, st)
+    R2 = dg.rhs(U2, st2)[:, :, :, :5]
+    err = (R - R2).abs().amax(dim=(1, 2, 3, 4, 5, 6)) / R2.abs().amax(dim=(1, 2, 3, 4, 5, 6))
+    assert float(err.max()) < 1e-12, err.tolist()
+
+
+@pytest.mark.parametrize("dim,p,eos,flux", [(2, 2, TM, 0), (3, 1, IDEAL, 1)])
+def test_closed_box_conserves_mass_and_energy(dim, p, eos, flux):
+    """Walls on every side: no mass or energy crosses the boundary (the HLL and HLLC
+    mass and energy fluxes vanish between a state and its mirror image)."""
+    from oracle.setup import REFLECT
+    st = Setup(dim=dim, p=p, n_elem=(4, 3, 3)[:dim] + (1,) * (3 - dim), eos=eos, bc=(REFLECT,) * 3, flux=flux)
+    U = _random_state(st, np.random.default_rng(70 + dim))
+    wR = dg.rhs(U, st) * dg.elem_weights(st)
+    tot = wR.sum((1, 2, 3, 4, 5, 6))
+    scale = wR.abs().sum((1, 2, 3, 4, 5, 6))
+    assert float(tot[0].abs() / scale[0]) < 1e-13 and float(tot[-1].abs() / scale[-1]) < 1e-13
+    # momentum is not conserved: the walls push back
+    assert float((tot[1:-1].abs() / scale[1:-1]).max()) > 1e-6
