@@ -372,18 +372,31 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
 #pragma unroll
     for (int v = 0; v < NV; ++v) lamWL[v] = lamWR[v] = 0.0;
     if (!have_B) {
-      // outflow: both HLL arguments are side A's trace
-      double lamWA[NV];
+      // outflow: both flux arguments are side A's trace; a wall: the exterior one is its
+      // mirror image (u_d negated), whose adjoint is mirrored back onto side A
+      const bool wall = sel3(d, m.reflect[0], m.reflect[1], m.reflect[2]) != 0;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) lamWA[v] = 0.0;
-      if constexpr (FLUX == FLUX_HLLC)
-        hllc_flux_rev<EOS, DIM>(WA, WA, d, q, lamFh, lamWA, lamWA, true, true);
-      else
-        hll_flux_rev<EOS, DIM>(WA, WA, d, q, lamFh, lamWA, lamWA, true, true);
+      for (int v = 0; v < NV; ++v) WB[v] = WA[v];
+      if (wall) comp_add<DIM>(WB + 1, d, -2.0 * comp<DIM>(WB + 1, d));
+      double WL[NV], WR[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        lamWL[v] = a_left ? lamWA[v] : 0.0;
-        lamWR[v] = a_left ? 0.0 : lamWA[v];
+        WL[v] = a_left ? WA[v] : WB[v];
+        WR[v] = a_left ? WB[v] : WA[v];
+      }
+      if constexpr (FLUX == FLUX_HLLC)
+        hllc_flux_rev<EOS, DIM>(WL, WR, d, q, lamFh, lamWL, lamWR, true, true);
+      else
+        hll_flux_rev<EOS, DIM>(WL, WR, d, q, lamFh, lamWL, lamWR, true, true);
+      double lamM[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lamM[v] = a_left ? lamWR[v] : lamWL[v];
+      if (wall) comp_add<DIM>(lamM + 1, d, -2.0 * comp<DIM>(lamM + 1, d));
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double lamWA = (a_left ? lamWL[v] : lamWR[v]) + lamM[v];
+        lamWL[v] = a_left ? lamWA : 0.0;
+        lamWR[v] = a_left ? 0.0 : lamWA;
       }
     } else {
       double WL[NV], WR[NV];

@@ -233,7 +233,8 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
     if (k >= d.dim) d.n_elem[k] = 1;
     if (d.n_elem[k] < 1) return bad("n_elem must be >= 1");
     if (k < d.dim && !(d.hi[k] > d.lo[k])) return bad("hi must exceed lo");
-    if (d.bc[k] != DG_BC_PERIODIC && d.bc[k] != DG_BC_OUTFLOW) return bad("bc must be periodic or outflow");
+    if (d.bc[k] != DG_BC_PERIODIC && d.bc[k] != DG_BC_OUTFLOW && d.bc[k] != DG_BC_REFLECT)
+      return bad("bc must be periodic, outflow or reflect");
   }
   if (d.eos != DG_EOS_IDEAL && d.eos != DG_EOS_TM) return bad("unknown eos");
   if (d.eos == DG_EOS_IDEAL && !(d.gamma_ad > 1.0)) return bad("gamma_ad must exceed 1");
@@ -274,6 +275,7 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   for (int k = 0; k < 3; ++k) {
     m.two_dx[k] = (k < d.dim) ? 2.0 * d.n_elem[k] / (d.hi[k] - d.lo[k]) : 0.0;
     m.periodic[k] = (d.bc[k] == DG_BC_PERIODIC) ? 1 : 0;
+    m.reflect[k] = (k < d.dim && d.bc[k] == DG_BC_REFLECT) ? 1 : 0;
   }
   const size_t bytes = sizeof(double) * (size_t)c->nv * (size_t)c->ntot;
   hipError_t e = hipSuccess;

@@ -49,6 +49,7 @@ struct MeshArgs {
   long long ntot;               // nodes per component
   double two_dx[3];             // 2 / dx_d
   int periodic[3];
+  int reflect[3];               // walls at both ends of dimension d (else outflow when not periodic)
 };
 
 // Event counters, one 64-byte set per slot.  A workgroup counts into slot
@@ -716,8 +717,10 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
       if (ge >= 0) {
         nfb += trace_glb<NV, P>(a.W + ge * NPE + (a_left ? bwd0 : fwd0), ntot, a_left ? -stride : stride, t, WB);
       } else {
+        // no neighbour: outflow (the interior trace) or a wall (its mirror image)
 #pragma unroll
         for (int v = 0; v < NV; ++v) WB[v] = WA[v];
+        if (sel3(d, m.reflect[0], m.reflect[1], m.reflect[2])) comp_add<DIM>(WB + 1, d, -2.0 * comp<DIM>(WB + 1, d));
       }
     }
     double WL[NV], WR[NV];
