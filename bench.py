@@ -354,6 +354,39 @@ def kh_growth(nx=256, orders=(0, 1, 2), t_end=3.0, sample_dt=0.05):
     return {"diagnostic": "fit of log <v_y^2> = A + r t over t in [1.5, 3]", "rows": out}
 
 
+def fp32_contract(steps=50):
+    """The 512x512 p=3 Taub-Matthews mesh in the FP32-contraction form against the same
+    mesh in FP64 on the same GPU: throughputs, speedup, RHS error and solution drift."""
+    from paper_2205_00095_amd import workloads as wl
+    n3 = steps
+    cfg3, s64, U64 = _setup("kh_tm_fp32", precision=wl.FP64)
+    U0 = U64.clone()
+    R64 = s64.rhs(U0)
+    t64 = _time_run(s64, U64, cfg3["dt"], n3, 5)
+    V64 = U0.clone()
+    s64.run(V64, cfg3["dt"], n3)
+    del s64, U64
+    cfg3, s32, U32 = _setup("kh_tm_fp32")
+    R32 = s32.rhs(U0)
+    t32 = _time_run(s32, U32, cfg3["dt"], n3, 5)
+    V32 = U0.clone()
+    s32.run(V32, cfg3["dt"], n3)
+    d3 = wl.n_dof(cfg3)
+    nv3 = R64.shape[0]
+    rhs_err = ((R32 - R64).reshape(nv3, -1).abs().max(1).values /
+               R64.reshape(nv3, -1).abs().max(1).values).max().item()
+    drift = ((V32 - V64).reshape(nv3, -1).abs().sum(1) / V64.reshape(nv3, -1).abs().sum(1)).max().item()
+    out = {
+        "workload": "kh_tm_fp32: 2D 512x512 elements p=3 TM EOS",
+        "value_fp32": d3 * n3 * 3 / t32, "value_fp64": d3 * n3 * 3 / t64,
+        "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": n3,
+        "rhs_rel_err_vs_fp64": rhs_err, "l1_drift_vs_fp64_after_steps": drift,
+        "note": "errors against the FP64 GPU path on the same input (that path matches the FP64 oracle "
+                "to 1e-12 in the parity tests); max over conserved variables"}
+    del s32, U32, R64, R32, V64, V32, U0
+    return out
+
+
 def cpu_baseline(kind="kh_tm", steps=3, seconds=10.0):
     """The oracle as it stands, on the host cores: `steps` SSP-RK3 steps of the full mesh,
     then as many more as fill about `seconds` of wall time in total (a bounded sample)."""
@@ -396,6 +429,10 @@ def main(argv=None):
                     help="only run the recovery-solver study of the paper's Sec. 3.3 and print its JSON")
     ap.add_argument("--kh-growth", action="store_true",
                     help="only run the KH growth-rate diagnostic of the paper's Sec. 4 and print its JSON")
+    ap.add_argument("--fp32-form", action="store_true",
+                    help="only run the FP32-contraction comparison (512x512 p=3) and print its JSON")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only run the adjoint cost measurement (128x128 p=2, 200 steps) and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -413,6 +450,12 @@ def main(argv=None):
         return 0
     if args.kh_growth:
         print(json.dumps(kh_growth()), flush=True)
+        return 0
+    if args.fp32_form:
+        print(json.dumps(fp32_contract(min(args.steps, 50))), flush=True)
+        return 0
+    if args.adjoint:
+        print(json.dumps(adjoint_ratio()), flush=True)
         return 0
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -486,32 +529,7 @@ def main(argv=None):
                     "f64_peak_frac": flops * dofs / stage_s / FP64_VECTOR_PEAK})
     if not args.no_extras and args.workload == "kh_tm":
         extras = {}
-        cfg3, s64, U64 = _setup("kh_tm_fp32", precision=wl.FP64)
-        n3 = min(args.steps, 50)
-        U0 = U64.clone()
-        R64 = s64.rhs(U0)
-        t64 = _time_run(s64, U64, cfg3["dt"], n3, 5)
-        V64 = U0.clone()
-        s64.run(V64, cfg3["dt"], n3)
-        del s64, U64
-        cfg3, s32, U32 = _setup("kh_tm_fp32")
-        R32 = s32.rhs(U0)
-        t32 = _time_run(s32, U32, cfg3["dt"], n3, 5)
-        V32 = U0.clone()
-        s32.run(V32, cfg3["dt"], n3)
-        d3 = wl.n_dof(cfg3)
-        nv3 = R64.shape[0]
-        rhs_err = ((R32 - R64).reshape(nv3, -1).abs().max(1).values /
-                   R64.reshape(nv3, -1).abs().max(1).values).max().item()
-        drift = ((V32 - V64).reshape(nv3, -1).abs().sum(1) / V64.reshape(nv3, -1).abs().sum(1)).max().item()
-        extras["fp32_contract"] = {
-            "workload": "kh_tm_fp32: 2D 512x512 elements p=3 TM EOS",
-            "value_fp32": d3 * n3 * 3 / t32, "value_fp64": d3 * n3 * 3 / t64,
-            "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": n3,
-            "rhs_rel_err_vs_fp64": rhs_err, "l1_drift_vs_fp64_after_steps": drift,
-            "note": "errors against the FP64 GPU path on the same input (that path matches the FP64 oracle "
-                    "to 1e-12 in the parity tests); max over conserved variables"}
-        del s32, U32, R64, R32, V64, V32, U0
+        extras["fp32_contract"] = fp32_contract(min(args.steps, 50))
         extras["hbm_copy_GBs"] = _copy_bandwidth() / 1e9
         extras["paper_sweep"] = paper_sweep()
         extras["other_configs"] = other_configs()
