@@ -13,8 +13,9 @@ Steps, in the order of Sec. 2.3:
         W^+ = sum_a l_a(+1) W_a,   W^- = sum_a l_a(-1) W_a  along d.
     Reading: a trace with rho <= 0 or P <= 0 is replaced by the primitive
     state of the node nearest to that face on the same line (counted);
- 4. exterior states: periodic neighbour, outflow (exterior = interior), or a
-    reflecting wall (the interior trace with its normal velocity negated);
+ 4. exterior states: periodic neighbour, outflow (exterior = interior), a
+    reflecting wall (the interior trace with its normal velocity negated) or a
+    fixed (Dirichlet) state, chosen per end of each dimension;
  5. HLL (or HLLC) numerical flux at every face point, Eq. (quad-surface-flux);
  6. lift with the inverse mass:
         S_i = -sum_d (2/dx_d)(1/w_{i_d}) [l_{i_d}(+1) Fhat^+ - l_{i_d}(-1) Fhat^-];
@@ -34,7 +35,7 @@ import torch
 
 from . import basis
 from .con2prim import con2prim
-from .setup import PERIODIC, REFLECT
+from .setup import DIRICHLET, PERIODIC, REFLECT
 from .srhd import face_flux, flux
 
 
@@ -79,13 +80,25 @@ def face_states(Wm, Wp, d, st):
     if st.bc[d] == PERIODIC:
         WL = torch.cat([last_p, Wp], ea)
         WR = torch.cat([Wm, first_m], ea)
-    elif st.bc[d] == REFLECT:  # a wall: the interior trace with its normal velocity negated
-        WL = torch.cat([_mirrored(first_m, d), Wp], ea)
-        WR = torch.cat([Wm, _mirrored(last_p, d)], ea)
-    else:  # outflow: exterior state equals the interior trace
-        WL = torch.cat([first_m, Wp], ea)
-        WR = torch.cat([Wm, last_p], ea)
+    else:
+        WL = torch.cat([_exterior(first_m, d, st, 0), Wp], ea)
+        WR = torch.cat([Wm, _exterior(last_p, d, st, 1)], ea)
     return WL, WR
+
+
+def _exterior(Wt, d, st, end):
+    """Exterior state at a boundary face from the interior trace Wt: outflow (the trace
+    itself), a reflecting wall (its mirror image) or a fixed (Dirichlet) state."""
+    kind = st.end_type(d, end)
+    if kind == REFLECT:
+        return _mirrored(Wt, d)
+    if kind == DIRICHLET:
+        from .srhd import u_from_v
+        rho, vx, vy, vz, P = st.bc_state[(d, end)]
+        u = u_from_v(torch.tensor([vx, vy, vz][:st.dim]), st.c)
+        w = torch.cat([torch.tensor([rho]), u, torch.tensor([P])])
+        return w.reshape((-1,) + (1,) * (Wt.dim() - 1)).expand_as(Wt).clone()
+    return Wt
 
 
 def _mirrored(W, d):

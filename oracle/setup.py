@@ -3,7 +3,7 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
-PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
+PERIODIC, OUTFLOW, REFLECT, DIRICHLET = 0, 1, 2, 3
 IDEAL, TM = 0, 1
 NEWTON, QUARTIC, CUBIC, BRENT = 0, 1, 2, 3
 HLL, HLLC = 0, 1
@@ -17,6 +17,8 @@ class Setup:
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (1.0, 1.0, 1.0)
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    bc_hi: tuple = (0, 0, 0)  # type at the upper end when it differs from bc[d]; 0 keeps bc[d]
+    bc_state: dict = field(default_factory=dict)  # (d, end) -> (rho, v_x, v_y, v_z, P) of a fixed end
     eos: int = IDEAL
     gamma_ad: float = 4.0 / 3.0
     c: float = 1.0
@@ -30,11 +32,16 @@ class Setup:
         return Setup(dim=cfg["dim"], p=cfg["p"], n_elem=tuple(cfg["n_elem"]), lo=tuple(cfg["lo"]),
                      hi=tuple(cfg["hi"]), bc=tuple(cfg["bc"]), eos=cfg["eos"],
                      gamma_ad=cfg["gamma_ad"], c=cfg["c"], c2p=cfg["c2p"],
-                     flux=cfg.get("flux", HLL))
+                     flux=cfg.get("flux", HLL), bc_hi=tuple(cfg.get("bc_hi", (0, 0, 0))),
+                     bc_state=dict(cfg.get("bc_state", {})))
 
     @property
     def nvar(self) -> int:
         return 2 + self.dim
+
+    def end_type(self, d: int, end: int) -> int:
+        """Boundary type at the lower (end 0) or upper (end 1) end of dimension d."""
+        return self.bc_hi[d] if end == 1 and self.bc_hi[d] != 0 else self.bc[d]
 
     def dx(self, d: int) -> float:
         return (self.hi[d] - self.lo[d]) / self.n_elem[d]

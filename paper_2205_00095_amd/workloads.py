@@ -29,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
+PERIODIC, OUTFLOW, REFLECT, DIRICHLET = 0, 1, 2, 3
 EOS_IDEAL, EOS_TM = 0, 1
 C2P_NEWTON, C2P_QUARTIC, C2P_CUBIC, C2P_BRENT = 0, 1, 2, 3
 FP64, FP32_CONTRACT = 0, 1

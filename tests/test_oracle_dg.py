@@ -200,3 +200,48 @@ def test_closed_box_conserves_mass_and_energy(dim, p, eos, flux):
     assert float(tot[0].abs() / scale[0]) < 1e-13 and float(tot[-1].abs() / scale[-1]) < 1e-13
     # momentum is not conserved: the walls push back
     assert float((tot[1:-1].abs() / scale[1:-1]).max()) > 1e-6
+
+
+def test_dirichlet_ends_take_the_fixed_state_in_the_flux():
+    """p = 0, three cells: the boundary fluxes are the numerical flux between the fixed
+    exterior state and the adjacent cell (fixed state on the outer side)."""
+    from oracle.setup import DIRICHLET, REFLECT
+    lo_state, hi_state = (2.0, 0.3, 0.0, 0.0, 1.5), (0.5, -0.2, 0.0, 0.0, 0.4)
+    st = Setup(dim=1, p=0, n_elem=(3, 1, 1), bc=(DIRICHLET, 0, 0), bc_hi=(DIRICHLET, 0, 0),
+               bc_state={(0, 0): lo_state, (0, 1): hi_state})
+    U = _random_state(st, np.random.default_rng(80))
+    W, _ = cp.con2prim(U, st)
+    R = dg.rhs(U, st)
+
+    def prim(s):
+        return torch.cat([torch.tensor([s[0]]), srhd.u_from_v(torch.tensor([s[1]]), 1.0), torch.tensor([s[4]])])[:, None]
+
+    Wc = [W[:, 0, 0, i, 0, 0, 0][:, None] for i in range(3)]
+    F = [srhd.hll(prim(lo_state), Wc[0], 0, st), srhd.hll(Wc[0], Wc[1], 0, st),
+         srhd.hll(Wc[1], Wc[2], 0, st), srhd.hll(Wc[2], prim(hi_state), 0, st)]
+    for i in range(3):
+        expect = -(F[i + 1] - F[i])[:, 0] / st.dx(0)
+        got = R[:, 0, 0, i, 0, 0, 0]
+        assert torch.allclose(got, expect, rtol=1e-13, atol=1e-13 * float(expect.abs().max())), (i, got, expect)
+    # a wall at the upper end instead: the mirror image is the exterior state there
+    st2 = Setup(dim=1, p=0, n_elem=(3, 1, 1), bc=(DIRICHLET, 0, 0), bc_hi=(REFLECT, 0, 0),
+                bc_state={(0, 0): lo_state})
+    R2 = dg.rhs(U, st2)
+    Wm = Wc[2].clone()
+    Wm[1] = -Wm[1]
+    expect = -(srhd.hll(Wc[2], Wm, 0, st) - F[2])[:, 0] / st.dx(0)
+    assert torch.allclose(R2[:, 0, 0, 2, 0, 0, 0], expect, rtol=1e-13, atol=1e-13 * float(expect.abs().max()))
+
+
+def test_uniform_state_with_matching_dirichlet_ends_is_steady():
+    from oracle.setup import DIRICHLET
+    v = (0.2, -0.1)
+    st = Setup(dim=2, p=2, n_elem=(4, 3, 1), eos=TM, bc=(DIRICHLET, DIRICHLET, 0),
+               bc_state={(d, e): (1.3, v[0], v[1], 0.0, 0.7) for d in range(2) for e in range(2)})
+    rho = torch.full(st.shape(), 1.3)
+    vel = torch.stack([torch.full(st.shape(), v[0]), torch.full(st.shape(), v[1])])
+    U = srhd.prim3_to_cons(rho, vel, torch.full(st.shape(), 0.7), st)
+    R = dg.rhs(U, st)
+    W, _ = cp.con2prim(U, st)
+    fmax = max(float(srhd.flux(W, d, st).abs().max()) * 2 / st.dx(d) for d in range(2))
+    assert float(R.abs().max()) <= 1e-13 * fmax * 9
