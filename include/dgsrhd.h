@@ -47,7 +47,7 @@ enum {
   DG_EAVERAGE = -5,     /* >= 1 flagged element had an inadmissible volume average */
   DG_ESTATE = -6        /* dg_set_state input had rho <= 0, P <= 0, |v| >= c or NaN */
 };
-enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1, DG_BC_REFLECT = 2 };
+enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1, DG_BC_REFLECT = 2, DG_BC_DIRICHLET = 3 };
 enum { DG_EOS_IDEAL = 0, DG_EOS_TM = 1 };
 enum { DG_C2P_DEFAULT = -1, DG_C2P_NEWTON = 0, DG_C2P_QUARTIC = 1, DG_C2P_CUBIC = 2, DG_C2P_BRENT = 3 };
 enum { DG_FP64 = 0, DG_FP32_CONTRACT = 1 };
@@ -57,10 +57,15 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
 /* Mesh and method description.  Cartesian mesh of n_elem[d] equal elements on
  * [lo[d], hi[d]] (Sec. 2.3), tensor-product Lagrange basis of order p on
  * Gauss-Legendre nodes with collocated quadrature (supported: dim 1..3,
- * p 0..3).  bc[d] applies to both ends of dimension d: periodic, outflow (the
- * exterior state at a boundary face is the interior trace) or a reflecting wall
- * (the interior trace with its velocity component along d negated; the walls of
- * the reflecting-wall test of Sec. 4).  eos / gamma_ad /
+ * p 0..3).  bc[d] is the boundary of dimension d: periodic, outflow (the
+ * exterior state at a boundary face is the interior trace), a reflecting wall
+ * (the interior trace with its velocity component along d negated) or Dirichlet
+ * (a fixed exterior state), the boundaries of the Riemann problems of Sec. 4.
+ * bc[d] applies to both ends unless bc_hi[d] (0 keeps bc[d]) names another
+ * non-periodic type for the upper end.  A Dirichlet end takes its exterior state
+ * from bc_state[d][end] = (rho, v_x, v_y, v_z, P), end 0 the lower, 1 the upper,
+ * v the 3-velocity (components beyond dim ignored); dg_init_mesh returns DG_EINVAL
+ * unless rho > 0, P > 0 and |v| < c there.  eos / gamma_ad /
  * c_light select the equation of state (Sec. 2.2).  c2p selects the recovery
  * solver of Sec. 3: ideal EOS NEWTON (Newton on the quartic in w, the default;
  * inside an SSP-RK stage started from the node's root of the previous stage,
@@ -91,6 +96,8 @@ typedef struct {
   double phys_eps;
   int sync_mode;
   int flux;
+  int bc_hi[3];
+  double bc_state[3][2][5];
 } dg_mesh_desc;
 
 typedef struct {

@@ -29,6 +29,8 @@ class MeshDesc(ctypes.Structure):
         ("phys", ctypes.c_int), ("phys_eps", ctypes.c_double),
         ("sync_mode", ctypes.c_int),
         ("flux", ctypes.c_int),
+        ("bc_hi", ctypes.c_int * 3),
+        ("bc_state", ctypes.c_double * 30),
     ]
 
 

@@ -372,12 +372,10 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
 #pragma unroll
     for (int v = 0; v < NV; ++v) lamWL[v] = lamWR[v] = 0.0;
     if (!have_B) {
-      // outflow: both flux arguments are side A's trace; a wall: the exterior one is its
-      // mirror image (u_d negated), whose adjoint is mirrored back onto side A
-      const bool wall = sel3(d, m.reflect[0], m.reflect[1], m.reflect[2]) != 0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) WB[v] = WA[v];
-      if (wall) comp_add<DIM>(WB + 1, d, -2.0 * comp<DIM>(WB + 1, d));
+      // a boundary face: the exterior state is side A's trace (outflow), its mirror image
+      // (a wall: u_d negated) or fixed; its adjoint goes back onto side A accordingly
+      const int kind = a_left ? sel3(d, m.bchi[0], m.bchi[1], m.bchi[2]) : sel3(d, m.bclo[0], m.bclo[1], m.bclo[2]);
+      exterior_state<DIM>(m, d, a_left, WA, WB);
       double WL[NV], WR[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -391,10 +389,11 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (vjp_min_waves<DIM, P, EOS>(
       double lamM[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) lamM[v] = a_left ? lamWR[v] : lamWL[v];
-      if (wall) comp_add<DIM>(lamM + 1, d, -2.0 * comp<DIM>(lamM + 1, d));
+      if (kind == BC_REFLECT) comp_add<DIM>(lamM + 1, d, -2.0 * comp<DIM>(lamM + 1, d));
+      const double keep = kind == BC_FIXED ? 0.0 : 1.0;  // a fixed state does not depend on A
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double lamWA = (a_left ? lamWL[v] : lamWR[v]) + lamM[v];
+        const double lamWA = (a_left ? lamWL[v] : lamWR[v]) + keep * lamM[v];
         lamWL[v] = a_left ? lamWA : 0.0;
         lamWR[v] = a_left ? 0.0 : lamWA;
       }

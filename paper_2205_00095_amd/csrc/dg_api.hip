@@ -233,8 +233,14 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
     if (k >= d.dim) d.n_elem[k] = 1;
     if (d.n_elem[k] < 1) return bad("n_elem must be >= 1");
     if (k < d.dim && !(d.hi[k] > d.lo[k])) return bad("hi must exceed lo");
-    if (d.bc[k] != DG_BC_PERIODIC && d.bc[k] != DG_BC_OUTFLOW && d.bc[k] != DG_BC_REFLECT)
-      return bad("bc must be periodic, outflow or reflect");
+    if (d.bc[k] != DG_BC_PERIODIC && d.bc[k] != DG_BC_OUTFLOW && d.bc[k] != DG_BC_REFLECT &&
+        d.bc[k] != DG_BC_DIRICHLET)
+      return bad("bc must be periodic, outflow, reflect or dirichlet");
+    if (k >= d.dim) d.bc_hi[k] = 0;
+    if (d.bc_hi[k] != 0 && d.bc_hi[k] != DG_BC_OUTFLOW && d.bc_hi[k] != DG_BC_REFLECT &&
+        d.bc_hi[k] != DG_BC_DIRICHLET)
+      return bad("bc_hi must be 0, outflow, reflect or dirichlet");
+    if (d.bc[k] == DG_BC_PERIODIC && d.bc_hi[k] != 0) return bad("a periodic dimension has no separate upper end");
   }
   if (d.eos != DG_EOS_IDEAL && d.eos != DG_EOS_TM) return bad("unknown eos");
   if (d.eos == DG_EOS_IDEAL && !(d.gamma_ad > 1.0)) return bad("gamma_ad must exceed 1");
@@ -275,7 +281,21 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   for (int k = 0; k < 3; ++k) {
     m.two_dx[k] = (k < d.dim) ? 2.0 * d.n_elem[k] / (d.hi[k] - d.lo[k]) : 0.0;
     m.periodic[k] = (d.bc[k] == DG_BC_PERIODIC) ? 1 : 0;
-    m.reflect[k] = (k < d.dim && d.bc[k] == DG_BC_REFLECT) ? 1 : 0;
+    m.bclo[k] = d.bc[k];
+    m.bchi[k] = d.bc_hi[k] != 0 ? d.bc_hi[k] : d.bc[k];
+    for (int end = 0; end < 2; ++end) {
+      const double* w = d.bc_state[k][end];
+      for (int i = 0; i < 5; ++i) m.bw[k][end][i] = 0.0;
+      if ((end == 0 ? m.bclo[k] : m.bchi[k]) != DG_BC_DIRICHLET || k >= d.dim) continue;
+      double v2 = 0.0;
+      for (int j = 0; j < d.dim; ++j) v2 += w[1 + j] * w[1 + j];
+      if (!(w[0] > 0.0) || !(w[4] > 0.0) || !(v2 < d.c_light * d.c_light))
+        return bad("a dirichlet end needs rho > 0, P > 0 and |v| < c");
+      const double g = 1.0 / std::sqrt(1.0 - v2 / (d.c_light * d.c_light));
+      m.bw[k][end][0] = w[0];
+      for (int j = 0; j < d.dim; ++j) m.bw[k][end][1 + j] = g * w[1 + j];
+      m.bw[k][end][4] = w[4];
+    }
   }
   const size_t bytes = sizeof(double) * (size_t)c->nv * (size_t)c->ntot;
   hipError_t e = hipSuccess;

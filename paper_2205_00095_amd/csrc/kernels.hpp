@@ -49,7 +49,8 @@ struct MeshArgs {
   long long ntot;               // nodes per component
   double two_dx[3];             // 2 / dx_d
   int periodic[3];
-  int reflect[3];               // walls at both ends of dimension d (else outflow when not periodic)
+  int bclo[3], bchi[3];         // non-periodic boundary type at the lower / upper end of d
+  double bw[3][2][5];           // fixed exterior primitives (rho, u_x, u_y, u_z, P) per d and end
 };
 
 // Event counters, one 64-byte set per slot.  A workgroup counts into slot
@@ -538,6 +539,28 @@ __device__ __forceinline__ int xcd_tile(int b, int nb, int rev = 0) {
   return x * q + min(x, r) + (rev ? cnt - 1 - k : k);
 }
 
+enum { BC_OUTFLOW = 1, BC_REFLECT = 2, BC_FIXED = 3 };
+
+// Exterior state at a boundary face of direction d from the interior trace Wi: outflow
+// (the trace), a reflecting wall (its mirror image, u_d negated) or a fixed state.
+// `upper` selects the end (the interior element lies below the face).
+template <int DIM>
+__device__ __forceinline__ void exterior_state(const MeshArgs& m, int d, bool upper, const double* Wi,
+                                               double* We) {
+  constexpr int NV = DIM + 2;
+  const int kind = upper ? sel3(d, m.bchi[0], m.bchi[1], m.bchi[2]) : sel3(d, m.bclo[0], m.bclo[1], m.bclo[2]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) We[v] = Wi[v];
+  if (kind == BC_REFLECT) comp_add<DIM>(We + 1, d, -2.0 * comp<DIM>(We + 1, d));
+  if (kind == BC_FIXED) {
+    const double* w = m.bw[d][upper ? 1 : 0];
+    We[0] = w[0];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) We[1 + j] = w[1 + j];
+    We[NV - 1] = w[4];
+  }
+}
+
 // Primitive trace at one point of an element face normal to d, interpolated along the
 // element's line of nodes through that point (Sec. 2.4 traces, reading R12 for the
 // fallback).  The weights are l_b(+1) taken over the nodes n0, n0 + step, ...,
@@ -717,10 +740,8 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
       if (ge >= 0) {
         nfb += trace_glb<NV, P>(a.W + ge * NPE + (a_left ? bwd0 : fwd0), ntot, a_left ? -stride : stride, t, WB);
       } else {
-        // no neighbour: outflow (the interior trace) or a wall (its mirror image)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) WB[v] = WA[v];
-        if (sel3(d, m.reflect[0], m.reflect[1], m.reflect[2])) comp_add<DIM>(WB + 1, d, -2.0 * comp<DIM>(WB + 1, d));
+        // no neighbour: a boundary face (side A's element is below it at the upper end)
+        exterior_state<DIM>(m, d, a_left, WA, WB);
       }
     }
     double WL[NV], WR[NV];

@@ -31,6 +31,11 @@ def _desc_from_config(cfg: dict, sync: bool) -> _lib.MeshDesc:
     d.phys_eps = float(cfg.get("phys_eps", 1e-12))
     d.sync_mode = 1 if sync else 0
     d.flux = int(cfg.get("flux", 0))
+    for k, t in enumerate(cfg.get("bc_hi", (0, 0, 0))):
+        d.bc_hi[k] = int(t)
+    for (k, end), state in cfg.get("bc_state", {}).items():
+        for i in range(5):
+            d.bc_state[(k * 2 + end) * 5 + i] = float(state[i])
     return d
 
 

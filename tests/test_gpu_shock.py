@@ -101,3 +101,37 @@ def test_paper_riemann_problems_converge_on_gpu(prob, rate):
     rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
     print(f"problem {prob}: L1(D) {e} rates {rates}", flush=True)
     assert rates[-1] > rate and e[1] < e[0], (e, rates)
+
+
+@pytest.mark.parametrize("flux,rho_tol", [(wl.FLUX_HLL, 1e-2), (wl.FLUX_HLLC, 1e-3)])
+def test_paper_wall_problem_as_specified_on_gpu(flux, rho_tol):
+    """The paper's wall problem as it states it: [0, 1], 400 cells, the inflow state fixed
+    at x = 0, a reflecting wall at x = 1, p = 0, to t = 1.5."""
+    from paper_2205_00095_amd.solver import Solver
+    c = _paper_wall_problem()
+    V, rho2, P2, D1 = _jump_state(c["gam"], c["v"], c["rho"], c["P"])
+    N = 400
+    cfg = wl.make_config("wave1d", n_elem=(N, 1, 1), p=0, bc=(wl.DIRICHLET, 0, 0), bc_hi=(wl.REFLECT, 0, 0),
+                         gamma_ad=c["gam"], bc_state={(0, 0): (c["rho"], c["v"], 0.0, 0.0, c["P"])})
+    cfg["flux"] = flux
+    print(f"case paper wall problem as specified, flux {flux}", flush=True)
+    shape = wl.field_shape(cfg)
+    s = Solver(cfg)
+    U = s.set_state(torch.from_numpy(wl.pack_primitives(np.full(shape, c["rho"]), np.full((1,) + shape, c["v"]),
+                                                        np.full(shape, c["P"]))).cuda())
+    dt = 0.1 / N
+    n = int(round(c["t"] / dt))
+    s.run(U, dt, n, order=1)
+    assert s.diagnostics()["c2p_fail"] == 0
+    W = s.con2prim(U).cpu().reshape(3, -1).numpy()
+    D = U[0].cpu().reshape(-1).numpy()
+    x = (np.arange(N) + 0.5) / N
+    xs = 1.0 + V * n * dt
+    L = 1.0 - xs
+    plateau = (x > xs + 0.2 * L) & (x < 1.0 - 0.2 * L)
+    rho_p, P_p = W[0][plateau].mean(), W[2][plateau].mean()
+    shock = x[np.where(D > 0.5 * (D1 + rho2))[0].min()]
+    print(f"plateau rho {rho_p:.6f} P {P_p:.6f}; shock at {shock:.5f} (exact {xs:.5f})", flush=True)
+    assert abs(rho_p / rho2 - 1.0) <= rho_tol
+    assert abs(P_p / P2 - 1.0) <= 1e-3
+    assert abs(shock - xs) <= 2.0 / N

@@ -127,3 +127,61 @@ def test_wall_vjp_matches_oracle_autograd(kind, over, flux):
     err = rel_err_per_var(got, ref)
     print(f"err {err.tolist()}", flush=True)
     assert float(err.max()) <= 1e-9, err.tolist()
+
+
+FIX = wl.DIRICHLET
+_STATES = {(0, 0): (1.2, 0.3, 0.05, 0.0, 0.9), (0, 1): (0.8, -0.1, 0.0, 0.0, 1.1),
+           (1, 0): (1.0, 0.0, 0.2, 0.0, 1.0), (1, 1): (0.9, 0.1, -0.25, 0.0, 1.2)}
+MIXED = [
+    ("wave1d", {"bc": (FIX, 0, 0), "bc_hi": (R, 0, 0), "bc_state": _STATES}, wl.FLUX_HLL),
+    ("wave1d", {"bc": (R, 0, 0), "bc_hi": (FIX, 0, 0), "bc_state": _STATES, "p": 3}, wl.FLUX_HLLC),
+    ("kh_tm", {"n_elem": (7, 6, 1), "bc": (FIX, R, 0), "bc_hi": (wl.OUTFLOW, FIX, 0), "bc_state": _STATES},
+     wl.FLUX_HLL),
+    ("kh_ideal", {"n_elem": (6, 5, 1), "bc": (FIX, FIX, 0), "bc_state": _STATES, "init": "kh"}, wl.FLUX_HLLC),
+]
+
+
+@pytest.mark.parametrize("kind,over,flux", MIXED)
+def test_mixed_ends_rhs_matches_oracle(kind, over, flux):
+    """Boundary types chosen per end (fixed states, walls, outflow) against the oracle."""
+    cfg = _cfg(kind, over, flux)
+    print(f"case mixed ends rhs {kind} flux {flux}", flush=True)
+    st, U = oracle_state(cfg)
+    R_ref = odg.rhs(U, st)
+    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    Rg = _solver(cfg).rhs(U.cuda()).cpu()
+    err = rel_err_per_var(Rg, R_ref)
+    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
+    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+
+
+@pytest.mark.parametrize("kind,over,flux", [MIXED[2], MIXED[3]])
+def test_mixed_ends_vjp_matches_oracle_autograd(kind, over, flux):
+    cfg = _cfg(kind, over, flux)
+    print(f"case mixed ends rhs_vjp {kind} flux {flux}", flush=True)
+    st, U = oracle_state(cfg)
+    g = torch.Generator().manual_seed(9)
+    lamR = torch.randn(U.shape, generator=g, dtype=torch.float64)
+
+    def ref_of(V):
+        Vr = V.clone().requires_grad_(True)
+        return torch.autograd.grad(odg.rhs(Vr, st), Vr, lamR)[0]
+
+    ref = ref_of(U)
+    sens = rel_err_per_var(ref_of(perturbed(U)), ref)
+    assert float(sens.max()) < 1e-10, f"test data sits on a derivative kink: {sens.tolist()}"
+    got = _solver(cfg).rhs_vjp(U.cuda(), lamR.cuda()).cpu()
+    err = rel_err_per_var(got, ref)
+    print(f"err {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9, err.tolist()
+
+
+def test_invalid_dirichlet_state_is_rejected():
+    from paper_2205_00095_amd.solver import Solver
+    cfg = _cfg("wave1d", {"bc": (FIX, 0, 0), "bc_state": {(0, 0): (1.0, 1.2, 0.0, 0.0, 1.0),
+                                                          (0, 1): (1.0, 0.0, 0.0, 0.0, 1.0)}}, wl.FLUX_HLL)
+    with pytest.raises(Exception):
+        Solver(cfg)
+    cfg = _cfg("wave1d", {"bc": (wl.PERIODIC, 0, 0), "bc_hi": (R, 0, 0)}, wl.FLUX_HLL)
+    with pytest.raises(Exception):
+        Solver(cfg)
