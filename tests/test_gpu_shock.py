@@ -135,3 +135,48 @@ def test_paper_wall_problem_as_specified_on_gpu(flux, rho_tol):
     assert abs(rho_p / rho2 - 1.0) <= rho_tol
     assert abs(P_p / P2 - 1.0) <= 1e-3
     assert abs(shock - xs) <= 2.0 / N
+
+
+def _gpu_l1_D_high(prob, N, p):
+    """L1 error of D (GL quadrature of the nodal values) after the paper's final time with
+    basis order p and SSP-RK order p + 1, HLLC, physicality operator on, no limiter."""
+    from paper_2205_00095_amd.solver import Solver
+    from ._exact import riemann_exact, riemann_problem
+    L, R, gam, t, _ = riemann_problem(prob)
+    cfg = wl.make_config("wave1d", n_elem=(N, 1, 1), p=p, bc=(wl.OUTFLOW,) * 3, gamma_ad=gam)
+    cfg["flux"] = wl.FLUX_HLLC
+    xi, w = np.polynomial.legendre.leggauss(p + 1)
+    x = (np.arange(N)[:, None] + 0.5 * (xi[None, :] + 1.0)) / N
+    shape = wl.field_shape(cfg)
+    pick = lambda a, b: np.where(x < 0.5, a, b).reshape(shape)  # noqa: E731
+    s = Solver(cfg)
+    U = s.set_state(torch.from_numpy(wl.pack_primitives(pick(L[0], R[0]), pick(L[1], R[1])[None],
+                                                        pick(L[2], R[2]))).cuda())
+    dt = 0.1 / (2 * p + 1) / N
+    n = int(round(t / dt))
+    s.run(U, dt, n, order=min(p + 1, 3))
+    d = s.diagnostics()
+    rho, v, _ = riemann_exact(L, R, gam)["profile"]((x - 0.5) / (n * dt))
+    De = rho / np.sqrt(1.0 - v * v)
+    D = U[0].cpu().reshape(N, p + 1).numpy()
+    return float((np.abs(D - De) * w[None, :]).sum() / (2 * N)), d
+
+
+@pytest.mark.parametrize("prob", [1, 4])
+@pytest.mark.parametrize("p", [1, 2])
+def test_high_order_through_shocks_with_the_operator_alone(prob, p):
+    """Basis orders 1 and 2 through the paper's mildly relativistic blast wave (problem 1)
+    and its Sod tube (problem 4) with the physicality operator and no limiter: every
+    recovery succeeds, no element average turns inadmissible, and the L1 error of D
+    falls with the mesh width (the operator smooths elements at the blast wave's shell
+    in problem 1).  The strong blast wave and the wall problem need the limiter the
+    paper adds at these orders (not built)."""
+    print(f"case Riemann problem {prob} at p = {p}", flush=True)
+    e1, d1 = _gpu_l1_D_high(prob, 200, p)
+    e2, d2 = _gpu_l1_D_high(prob, 400, p)
+    print(f"problem {prob} p {p}: L1(D) {e1:.4e} -> {e2:.4e}; diagnostics {d2}", flush=True)
+    for d in (d1, d2):
+        assert d["c2p_fail"] == 0 and d["bad_average"] == 0
+    assert e2 < 0.8 * e1, (e1, e2)
+    if prob == 1:
+        assert d2["smoothed"] > 0
