@@ -1,0 +1,86 @@
+"""The paper's first 2D Riemann problem (Sec. 4, 2D Riemann problems: four quadrant
+states, Gamma = 5/3, outflow boundaries, t = 0.8; tests/golden/riemann_problem_2d_test1.txt)
+on the GPU: parity with the oracle over the first steps, and the full run at p = 0 and
+p = 1 (physicality operator on, no limiter) staying admissible and symmetric about the
+diagonal, as its initial data are (quadrants 2 and 4 are mirror images)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import timestep as ots
+from paper_2205_00095_amd import workloads as wl
+
+from ._util import oracle_state, parity_tol, rel_err_per_var
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem():
+    path = os.path.join(os.path.dirname(__file__), "golden", "riemann_problem_2d_test1.txt")
+    with open(path) as fh:
+        rows = [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+    quads = {int(r[0]): [float(v) for v in r[1:]] for r in rows if r[0] != "G"}
+    gam, t = (float(v) for v in [r for r in rows if r[0] == "G"][0][1:])
+    return quads, gam, t
+
+
+def _setup(N, p):
+    quads, gam, t = _problem()
+    cfg = wl.make_config("kh_ideal", n_elem=(N, N, 1), p=p, lo=(-1.0, -1.0, 0.0), hi=(1.0, 1.0, 1.0),
+                         bc=(wl.OUTFLOW,) * 3, gamma_ad=gam)
+    cfg["flux"] = wl.FLUX_HLLC
+    cfg["precision"] = wl.FP64
+    xi, _ = np.polynomial.legendre.leggauss(p + 1)
+    c = -1.0 + 2.0 * (np.arange(N)[:, None] + 0.5 * (xi[None, :] + 1.0)) / N  # [element, node]
+    X, Y = np.broadcast_arrays(c[None, :, None, :], c[:, None, :, None])    # [ey, ex, j, i]
+    quad = np.where(X >= 0, np.where(Y >= 0, 1, 4), np.where(Y >= 0, 2, 3))
+    shape = wl.field_shape(cfg)
+    field = [np.choose(quad - 1, [quads[q][k] for q in (1, 2, 3, 4)]).reshape(shape) for k in range(4)]
+    prims = wl.pack_primitives(field[0], np.stack([field[1], field[2]]), field[3])
+    return cfg, prims, t
+
+
+def test_first_steps_match_oracle():
+    from oracle import srhd
+    from oracle.setup import Setup
+    cfg, prims, _ = _setup(16, 1)
+    print("case 2D Riemann test 1, 16x16 p=1, 6 steps", flush=True)
+    st = Setup.from_config(cfg)
+    P = torch.from_numpy(prims)
+    U = srhd.prim3_to_cons(P[0], P[1:3], P[3], st).contiguous()
+    U_ref = ots.run(U, cfg["dt"], 6, st, phys=True, order=2)
+    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], 6, st, phys=True, order=2), U)
+    from paper_2205_00095_amd.solver import Solver
+    Ud = U.cuda()
+    Solver(cfg).run(Ud, cfg["dt"], 6, order=2)
+    err = rel_err_per_var(Ud.cpu(), U_ref)
+    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
+    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+
+
+@pytest.mark.parametrize("N,p", [(256, 0), (128, 1)])
+def test_full_run_admissible_and_symmetric(N, p):
+    from paper_2205_00095_amd.solver import Solver
+    cfg, prims, t = _setup(N, p)
+    print(f"case 2D Riemann test 1, {N}x{N} p={p} to t={t}", flush=True)
+    s = Solver(cfg)
+    U = s.set_state(torch.from_numpy(prims).cuda())
+    dt = 0.1 / (2 * p + 1) * (2.0 / N)
+    n = int(round(t / dt))
+    s.run(U, dt, n, order=min(p + 1, 3))
+    d = s.diagnostics()
+    print(f"{n} steps, diagnostics {d}", flush=True)
+    assert d["c2p_fail"] == 0 and d["bad_average"] == 0
+    if p > 0:
+        assert d["smoothed"] > 0  # the operator is what keeps p = 1 admissible here
+    Uc = U.cpu()[:, 0, :, :, 0]  # [var, ey, ex, j, i]
+    Ut = Uc.permute(0, 2, 1, 4, 3)
+    mirror = torch.stack([Ut[0], Ut[2], Ut[1], Ut[3]])  # swap x and y, and S_x with S_y
+    asym = float((Uc - mirror).abs().max() / Uc.abs().max())
+    print(f"asymmetry about the diagonal {asym:.2e}", flush=True)
+    # p = 0: symmetric to rounding; p = 1: the trace fallbacks and the operator take
+    # discrete per-element decisions (thresholds, argmin) that turn rounding differences
+    # between the x and y sweeps into small asymmetries, still far below the flow's scales
+    assert asym <= (1e-12 if p == 0 else 1e-4)
