@@ -46,3 +46,36 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert lib.dg_init_mesh(None, None, ctypes.byref(out)) == _lib.DG_EINVAL
     assert lib.dg_rhs(None, None, None) == _lib.DG_EINVAL
     assert lib.dg_last_error(None) == b"null context"
+
+
+def _desc(**over):
+    """A valid 1D description through the Python binding (nothing is allocated here)."""
+    from paper_2205_00095_amd import workloads as wl
+    from paper_2205_00095_amd.solver import _desc_from_config
+    cfg = wl.make_config("wave1d", **over)
+    return _desc_from_config(cfg, False)
+
+
+@pytest.mark.parametrize("change", [
+    {"p": 5},                                                     # unsupported order
+    {"flux": 7},                                                  # unknown flux
+    {"bc": (0, 0, 0), "bc_hi": (2, 0, 0)},                        # a periodic dimension has no upper end
+    {"bc": (3, 0, 0), "bc_state": {(0, 0): (-1.0, 0.0, 0.0, 0.0, 1.0), (0, 1): (1.0, 0.0, 0.0, 0.0, 1.0)}},
+    {"bc": (3, 0, 0), "bc_state": {(0, 0): (1.0, 1.5, 0.0, 0.0, 1.0), (0, 1): (1.0, 0.0, 0.0, 0.0, 1.0)}},
+    {"bc": (1, 0, 0), "bc_hi": (3, 0, 0)},                        # a Dirichlet end without its state
+])
+def test_invalid_descriptions_are_rejected_without_a_gpu(change):
+    """Validation runs on the host before any device call; the checks read the fields the
+    binding fills, so a layout mismatch between the binding and the header shows here."""
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2205_00095_amd import _lib
+    lib = _lib.load()
+    over = dict(change)
+    flux = over.pop("flux", None)
+    d = _desc(**over)
+    if flux is not None:
+        d.flux = flux
+    out = ctypes.c_void_p()
+    assert lib.dg_init_mesh(ctypes.byref(d), None, ctypes.byref(out)) == _lib.DG_EINVAL
+    assert not out.value
