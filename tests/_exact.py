@@ -207,3 +207,144 @@ def riemann_problem(i):
                 for ln in fh if ln.strip() and not ln.startswith("#")}
     r = rows[i]
     return (r[0], r[1], r[3]), (r[4], r[5], r[7]), r[8], r[9], (r[2], r[6])
+
+
+# ---------------------------------------------------------------------------------
+# The same with a transverse velocity v_t (Pons, Marti & Mueller 2000): across every
+# wave but the contact h W v_t is constant; in a rarefaction
+#   dv_x/dp = +- 1 / (rho h W^2 c_s sqrt(1 + g)),  g = v_t^2 (xi^2 - 1) / (1 - xi v_x)^2,
+# xi the characteristic speed, integrated numerically.  The tests check the jump
+# conditions of all four conserved components across the shocks and the self-similar
+# equation F' = xi U' inside the fans.
+
+def _char_speed(vx, vt, c, sign):
+    v2 = vx * vx + vt * vt
+    root = c * math.sqrt((1.0 - v2) * (1.0 - v2 * c * c - vx * vx * (1.0 - c * c)))
+    return (vx * (1.0 - c * c) + sign * root) / (1.0 - v2 * c * c)
+
+
+def _vt_of(A, h, vx):
+    W = math.sqrt((1.0 + A * A / (h * h)) / (1.0 - vx * vx))
+    return A / (h * W)
+
+
+def _side_t(state, p, gam, sign):
+    """(v_x, v_t, rho) reached from state = (rho, v_x, v_t, p) at pressure p."""
+    rho_a, vx_a, vt_a, p_a = state
+    h_a = _h(rho_a, p_a, gam)
+    W_a = 1.0 / math.sqrt(1.0 - vx_a * vx_a - vt_a * vt_a)
+    A = h_a * W_a * vt_a
+    if p > p_a:  # shock
+        k = (gam - 1.0) / (gam * p)
+
+        def taub(hb):
+            return hb * hb - h_a * h_a - (hb * (hb - 1.0) * k + h_a / rho_a) * (p - p_a)
+
+        hi = 2.0
+        while taub(hi) < 0.0:
+            hi *= 2.0
+        h_b = brentq(taub, 1.0 + 1e-15, hi, xtol=1e-15, rtol=1e-15)
+        rho_b = gam * p / ((gam - 1.0) * (h_b - 1.0))
+        j2 = -(p - p_a) / (h_b / rho_b - h_a / rho_a)
+        D2 = rho_a * rho_a * W_a * W_a
+        Vs = (D2 * vx_a + sign * math.sqrt(j2) * math.sqrt(j2 + D2 * (1.0 - vx_a * vx_a))) / (D2 + j2)
+        j = sign * math.sqrt(j2)
+        Ws = 1.0 / math.sqrt(1.0 - Vs * Vs)
+        vx_b = (h_a * W_a * vx_a + Ws * (p - p_a) / j) / (h_a * W_a + (p - p_a) * (Ws * vx_a / j + 1.0 / (rho_a * W_a)))
+        return vx_b, _vt_of(A, h_b, vx_b), rho_b
+    from scipy.integrate import solve_ivp
+
+    def rhs(q, y):
+        vx = y[0]
+        r = rho_a * (q / p_a) ** (1.0 / gam)
+        h = _h(r, q, gam)
+        c = _cs(r, q, gam)
+        vt = _vt_of(A, h, vx)
+        W2 = 1.0 / (1.0 - vx * vx - vt * vt)
+        xi = _char_speed(vx, vt, c, sign)
+        g = vt * vt * (xi * xi - 1.0) / (1.0 - xi * vx) ** 2
+        return [sign * 1.0 / (r * h * W2 * c * math.sqrt(1.0 + g))]
+
+    if p == p_a:
+        return vx_a, vt_a, rho_a
+    sol = solve_ivp(rhs, (p_a, p), [vx_a], rtol=1e-12, atol=1e-14, method="DOP853")
+    vx = float(sol.y[0, -1])
+    rho = rho_a * (p / p_a) ** (1.0 / gam)
+    return vx, _vt_of(A, _h(rho, p, gam), vx), rho
+
+
+def riemann_exact_t(left, right, gam):
+    """Star states and a sampler xi -> (rho, v_x, v_t, p) for left/right = (rho, v_x, v_t, p).
+    The left wave uses sign -1 (its characteristic xi_-), the right one +1."""
+    def gap(p):
+        try:
+            return _side_t(left, p, gam, -1)[0] - _side_t(right, p, gam, +1)[0]
+        except ValueError:  # a rarefaction towards vacuum leaves the physical range: gap > 0 there
+            return 1.0
+
+    lo, hi = 1e-6 * min(left[3], right[3]), 10.0 * max(left[3], right[3])
+    while gap(hi) > 0.0:
+        hi *= 10.0
+    ps = brentq(gap, lo, hi, xtol=1e-300, rtol=1e-14)
+    vxs, vtL, rhoL = _side_t(left, ps, gam, -1)
+    _, vtR, rhoR = _side_t(right, ps, gam, +1)
+
+    def wave_speeds(state, vt_s, rho_s, sign):
+        rho_a, vx_a, vt_a, p_a = state
+        if ps > p_a:
+            h_a = _h(rho_a, p_a, gam)
+            W_a = 1.0 / math.sqrt(1.0 - vx_a * vx_a - vt_a * vt_a)
+            h_b = _h(rho_s, ps, gam)
+            j2 = -(ps - p_a) / (h_b / rho_s - h_a / rho_a)
+            D2 = rho_a * rho_a * W_a * W_a
+            Vs = (D2 * vx_a + sign * math.sqrt(j2) * math.sqrt(j2 + D2 * (1.0 - vx_a * vx_a))) / (D2 + j2)
+            return Vs, Vs
+        return (_char_speed(vx_a, vt_a, _cs(rho_a, p_a, gam), sign),
+                _char_speed(vxs, vt_s, _cs(rho_s, ps, gam), sign))
+
+    lh, lt = wave_speeds(left, vtL, rhoL, -1)
+    rh, rt = wave_speeds(right, vtR, rhoR, +1)
+    tables = {}
+
+    def fan_table(state, sign, n=1500):
+        import numpy as np
+        rows = []
+        for q in np.geomspace(state[3], ps, n):
+            vx, vt, rho = _side_t(state, q, gam, sign)
+            rows.append((_char_speed(vx, vt, _cs(rho, q, gam), sign), rho, vx, vt, q))
+        return np.array(sorted(rows))
+
+    def profile(xi):
+        import numpy as np
+        xi = np.asarray(xi, dtype=float)
+        out = np.empty((4,) + xi.shape)
+        for m, val in [(xi < lh, left), ((xi >= lt) & (xi < vxs), (rhoL, vxs, vtL, ps)),
+                       ((xi >= vxs) & (xi < rt), (rhoR, vxs, vtR, ps)), (xi >= rh, right)]:
+            for q in range(4):
+                out[q][m] = val[q]
+        for sign, state, a, b in ((-1, left, lh, lt), (+1, right, rt, rh)):
+            m = (xi >= a) & (xi < b)
+            if ps < state[3] and m.any():
+                if sign not in tables:
+                    tables[sign] = fan_table(state, sign)
+                tab = tables[sign]
+                for q in range(4):
+                    out[q][m] = np.interp(xi[m], tab[:, 0], tab[:, 1 + q])
+        return out
+
+    def sample(xi):
+        """(rho, v_x, v_t, p) at one xi, fans solved pointwise (slow; for checks)."""
+        for sign, state, a, b in ((-1, left, lh, lt), (+1, right, rt, rh)):
+            if ps < state[3] and min(a, b) <= xi <= max(a, b):
+                def f(q):
+                    vx, vt, rho = _side_t(state, q, gam, sign)
+                    return _char_speed(vx, vt, _cs(rho, q, gam), sign) - xi
+
+                q = brentq(f, min(ps, state[3]), max(ps, state[3]), xtol=1e-300, rtol=1e-13)
+                vx, vt, rho = _side_t(state, q, gam, sign)
+                return rho, vx, vt, q
+        return tuple(float(v) for v in profile(np.array([xi]))[:, 0])
+
+    import numpy as np
+    return {"p_star": ps, "vx_star": vxs, "left": (rhoL, vtL), "right": (rhoR, vtR),
+            "left_speeds": (lh, lt), "right_speeds": (rt, rh), "profile": profile, "sample": sample}

@@ -75,3 +75,63 @@ def test_oracle_first_order_converges_to_the_exact_solution(prob, rate):
     reduced rate discontinuities allow)."""
     e1, e2 = _l1_D(prob, 100), _l1_D(prob, 200)
     assert math.log2(e1 / e2) > rate, (e1, e2)
+
+
+def _cons_flux_t(rho, vx, vt, p, gam):
+    h = 1.0 + gam / (gam - 1.0) * p / rho
+    W = 1.0 / math.sqrt(1.0 - vx * vx - vt * vt)
+    D, Sx, St, E = rho * W, rho * h * W * W * vx, rho * h * W * W * vt, rho * h * W * W - p
+    return np.array([D, Sx, St, E]), np.array([D * vx, Sx * vx + p, St * vx, (E + p) * vx])
+
+
+@pytest.mark.parametrize("prob", [1, 3, 4])
+def test_exact_solution_with_transverse_velocity_is_consistent(prob):
+    """The general solution (transverse velocity allowed): it reproduces the solution
+    without transverse velocity where there is none, its shocks satisfy the jump
+    conditions of all four conserved components, and inside its fans the self-similar
+    equation dF/dxi = xi dU/dxi holds (checked by central differences)."""
+    from ._exact import riemann_exact_t
+    L, R, gam, t, vy = riemann_problem(prob)
+    left, right = (L[0], L[1], vy[0], L[2]), (R[0], R[1], vy[1], R[2])
+    s = riemann_exact_t(left, right, gam)
+    if vy == (0.0, 0.0):
+        s0 = riemann_exact(L, R, gam)
+        assert abs(s["p_star"] / s0["p_star"] - 1.0) < 1e-10 and abs(s["vx_star"] - s0["v_star"]) < 1e-10
+    ps, vxs = s["p_star"], s["vx_star"]
+    for sign, state, (rho_s, vt_s), (a, b) in ((-1, left, s["left"], s["left_speeds"]),
+                                                (+1, right, s["right"], s["right_speeds"])):
+        if ps > state[3]:  # shock
+            U0, F0 = _cons_flux_t(*state, gam)
+            U1, F1 = _cons_flux_t(rho_s, vxs, vt_s, ps, gam)
+            res = np.abs((F1 - F0) - a * (U1 - U0)) / (np.abs(F1) + np.abs(F0) + np.abs(U1) + np.abs(U0) + 1e-300)
+            assert float(res.max()) < 1e-10, (prob, sign, res)
+        else:  # fan: F' = xi U' at interior points
+            lo_, hi_ = min(a, b), max(a, b)
+            for xi in np.linspace(lo_, hi_, 7)[2:-2]:
+                e = 1e-4 * (hi_ - lo_)
+                Um, Fm = _cons_flux_t(*s["sample"](xi - e), gam)
+                Up, Fp = _cons_flux_t(*s["sample"](xi + e), gam)
+                dU, dF = (Up - Um) / (2 * e), (Fp - Fm) / (2 * e)
+                scale = np.abs(dF).max() + abs(xi) * np.abs(dU).max()
+                assert float(np.abs(dF - xi * dU).max()) < 1e-6 * scale, (prob, xi, dF, xi * dU)
+
+
+def test_transverse_rarefaction_is_self_similar():
+    """A rarefaction carrying transverse velocity (the term the paper's problems do not
+    exercise on their fan side): F' = xi U' inside it, and h W v_t constant across it."""
+    from ._exact import riemann_exact_t
+    gam = 5.0 / 3.0
+    left, right = (1.0, 0.1, 0.5, 10.0), (1.0, 0.0, -0.3, 0.1)
+    s = riemann_exact_t(left, right, gam)
+    a, b = s["left_speeds"]
+    assert s["p_star"] < left[3] and b > a
+    h = lambda r, p: 1.0 + gam / (gam - 1.0) * p / r  # noqa: E731
+    A0 = h(left[0], left[3]) * left[2] / math.sqrt(1.0 - left[1] ** 2 - left[2] ** 2)
+    for xi in np.linspace(a, b, 7)[1:-1]:
+        e = 1e-4 * (b - a)
+        Um, Fm = _cons_flux_t(*s["sample"](xi - e), gam)
+        Up, Fp = _cons_flux_t(*s["sample"](xi + e), gam)
+        dU, dF = (Up - Um) / (2 * e), (Fp - Fm) / (2 * e)
+        assert float(np.abs(dF - xi * dU).max()) < 1e-6 * (np.abs(dF).max() + abs(xi) * np.abs(dU).max())
+        rho, vx, vt, p = s["sample"](xi)
+        assert abs(h(rho, p) * vt / math.sqrt(1.0 - vx * vx - vt * vt) / A0 - 1.0) < 1e-9

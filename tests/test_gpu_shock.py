@@ -180,3 +180,39 @@ def test_high_order_through_shocks_with_the_operator_alone(prob, p):
     assert e2 < 0.8 * e1, (e1, e2)
     if prob == 1:
         assert d2["smoothed"] > 0
+
+
+def _gpu_l1_D_transverse(N):
+    """The paper's Riemann problem 3 (transverse velocity 0.99c on the right) on an N x 1
+    mesh of the 2D code (y periodic, the state uniform in y), p = 0, HLLC, RK1."""
+    from paper_2205_00095_amd.solver import Solver
+    from ._exact import riemann_exact_t, riemann_problem
+    L, R, gam, t, vy = riemann_problem(3)
+    cfg = wl.make_config("kh_ideal", n_elem=(N, 1, 1), p=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0 / N, 1.0),
+                         bc=(wl.OUTFLOW, wl.PERIODIC, wl.PERIODIC), gamma_ad=gam)
+    cfg["flux"] = wl.FLUX_HLLC
+    shape = wl.field_shape(cfg)
+    x = (np.arange(N) + 0.5) / N
+    pick = lambda a, b: np.where(x < 0.5, a, b).reshape(shape)  # noqa: E731
+    s = Solver(cfg)
+    v = np.stack([pick(L[1], R[1]), pick(vy[0], vy[1])])
+    U = s.set_state(torch.from_numpy(wl.pack_primitives(pick(L[0], R[0]), v, pick(L[2], R[2]))).cuda())
+    dt = 0.1 / N
+    n = int(round(t / dt))
+    s.run(U, dt, n, order=1)
+    assert s.diagnostics()["c2p_fail"] == 0
+    sub = (np.arange(N)[:, None] + (np.arange(16)[None, :] + 0.5) / 16) / N
+    rho, vx, vt, _ = riemann_exact_t((L[0], L[1], vy[0], L[2]), (R[0], R[1], vy[1], R[2]), gam)["profile"](
+        (sub - 0.5) / (n * dt))
+    De = (rho / np.sqrt(1.0 - vx * vx - vt * vt)).mean(1)
+    return float(np.abs(U[0].cpu().reshape(-1).numpy() - De).mean())
+
+
+def test_paper_riemann_problem_3_converges_on_gpu():
+    """Problem 3 (the strong blast wave into gas moving transversally at 0.99c) at p = 0
+    against the exact solution with transverse velocity: the L1 error of D falls."""
+    print("case Riemann problem 3", flush=True)
+    e = [_gpu_l1_D_transverse(N) for N in (800, 1600, 3200)]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    print(f"problem 3: L1(D) {e} rates {rates}", flush=True)
+    assert e[2] < e[1] < e[0] and rates[-1] > 0.3, (e, rates)
