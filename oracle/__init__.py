@@ -15,12 +15,13 @@ Each step follows the paper in its order and notation:
 * ``basis``        nodal Lagrange basis on Gauss-Legendre nodes (Sec. 2.3)
 * ``eos``          ideal and Taub-Matthews equations of state (Sec. 2.2)
 * ``srhd``         primitive-to-conserved map, fluxes (Sec. 2.1), wavespeeds
-                   and the HLL numerical flux (Sec. 2.4)
+                   and the HLL and HLLC numerical fluxes (Sec. 2.4)
 * ``con2prim``     the four conserved-to-primitive solvers (Sec. 3.1, 3.2)
 * ``dg``           the DG weak-form right-hand side (Sec. 2.3, Eqs. for the
-                   volume and surface quadratures)
+                   volume and surface quadratures) with periodic, outflow,
+                   reflecting-wall and fixed-state boundaries
 * ``physicality``  the physicality-enforcing operator (Sec. 2.5)
-* ``timestep``     SSP-RK3 with the operator after each stage (Sec. 2.3)
+* ``timestep``     SSP-RK1/2/3 with the operator after each stage (Sec. 2.3)
 * ``objective``    the integral of v_y^2 (the Kelvin-Helmholtz diagnostic)
 
 Parity status per function is stated in each module header; the only
