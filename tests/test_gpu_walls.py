@@ -138,6 +138,8 @@ MIXED = [
     ("kh_tm", {"n_elem": (7, 6, 1), "bc": (FIX, R, 0), "bc_hi": (wl.OUTFLOW, FIX, 0), "bc_state": _STATES},
      wl.FLUX_HLL),
     ("kh_ideal", {"n_elem": (6, 5, 1), "bc": (FIX, FIX, 0), "bc_state": _STATES, "init": "kh"}, wl.FLUX_HLLC),
+    ("random3d", {"n_elem": (3, 3, 2), "p": 1, "bc": (R, wl.OUTFLOW, FIX), "bc_hi": (FIX, 0, R),
+                  "bc_state": {**_STATES, (2, 0): (0.7, 0.1, 0.0, 0.3, 0.5)}}, wl.FLUX_HLL),
 ]
 
 
