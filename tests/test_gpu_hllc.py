@@ -178,3 +178,31 @@ def test_hllc_fullsize_rhs():
     err = rel_err_per_var(R, R_ref)
     print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
     assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+
+
+def test_hllc_trajectory_gradient_matches_oracle():
+    """dJ/d(initial primitives) through 4 HLLC steps (checkpoint every 3) against the
+    oracle's reverse mode through its HLLC."""
+    from oracle import objective as oobj
+    from oracle import srhd as osrhd
+    from oracle.setup import Setup
+    from paper_2205_00095_amd.adjoint import vy2_after
+    cfg = _cfg("kh_ideal", {"n_elem": (4, 4, 1)})
+    print("case hllc trajectory gradient", flush=True)
+    st = Setup.from_config(cfg)
+    rho, v, P = wl.initial_primitives(cfg)
+    v = v.copy()
+    v[1] += wl.kh_perturbation(cfg)
+    src = torch.from_numpy(wl.pack_primitives(rho, v, P))
+    dt = cfg["dt"] * 10
+    s_r = src.clone().requires_grad_(True)
+    U = osrhd.prim3_to_cons(s_r[0], s_r[1:3], s_r[3], st)
+    Jref = oobj.vy2_integral(ots.run(U, dt, 4, st), st)
+    (gref,) = torch.autograd.grad(Jref, s_r)
+    sd = src.cuda().requires_grad_(True)
+    J = vy2_after(_solver(cfg), sd, 4, dt, k=3)
+    J.backward()
+    assert abs(float(J) - float(Jref)) <= 1e-12 * abs(float(Jref))
+    err = rel_err_per_var(sd.grad.cpu(), gref)
+    print(f"err {err.tolist()}", flush=True)
+    assert float(err.max()) <= 1e-9
