@@ -27,7 +27,10 @@ discrete conservation on a periodic mesh, mirror and axis-swap symmetries, a
 finite-volume update written independently, a reflecting wall equals a periodic
 mesh of twice the size holding the mirrored state, a closed box conserves mass
 and energy, and (test_oracle_timestep.py) order ~p+1 on the exact translated
-density wave.
+density wave.  The trace fallback of step 3 is pinned by element lines whose
+interpolated density (1D, - face) or pressure (2D, + face along y) goes
+negative: that face point carries the nearest node's primitives bit for bit and
+is counted once.
 """
 from __future__ import annotations
 

@@ -5,6 +5,12 @@ growth phase); J is that integral without the 1/|Omega| factor, evaluated with
 the collocated GL quadrature: J = sum_e sum_i (prod_d dx_d/2) w_i v_y,i^2,
 v_y = u_y / gamma from the recovered primitives.  Its gradient is taken by
 torch autograd through con2prim (the oracle's reverse mode).
+
+Pinned by tests/test_oracle_objective.py against closed-form integrals: a
+uniform v_y gives v_y^2 x area (2D and 3D), a separable polynomial field of
+degree <= p per element gives its exact integral, and A sin(2 pi x) gives A^2
+on the Kelvin-Helmholtz domain (a dropped Jacobian factor, a missing weight or
+u_y in place of v_y fails them).
 """
 from __future__ import annotations
 

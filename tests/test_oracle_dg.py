@@ -245,3 +245,61 @@ def test_uniform_state_with_matching_dirichlet_ends_is_steady():
     W, _ = cp.con2prim(U, st)
     fmax = max(float(srhd.flux(W, d, st).abs().max()) * 2 / st.dx(d) for d in range(2))
     assert float(R.abs().max()) <= 1e-13 * fmax * 9
+
+
+# ---- reading R12: a trace whose interpolated rho or P is <= 0 takes the primitive
+# state of the node nearest that face on the same line, and is counted
+
+def _prims_from_nodes(st, rho, v, P):
+    return srhd.prim3_to_cons(torch.tensor(rho), torch.tensor(v), torch.tensor(P), st)
+
+
+def test_trace_fallback_density_1d():
+    """p = 2: l(-1) = (1.4789, -0.6667, 0.1878) on the GL nodes, so node densities
+    (0.01, 1, 1) interpolate to about -0.46 at x = -1: the - trace must equal node 0's
+    primitives exactly; the + trace (about 0.81) is the interpolant itself."""
+    st = Setup(dim=1, p=2, n_elem=(3, 1, 1), eos=IDEAL)
+    shape = st.shape()
+    rho = np.ones(shape)
+    rho[0, 0, 1, 0, 0, :] = (0.01, 1.0, 1.0)   # element 1
+    v = np.full((1,) + shape, 0.2)
+    P = np.full(shape, 0.5)
+    U = _prims_from_nodes(st, rho, v, P)
+    W, _ = cp.con2prim(U, st)
+    Wm, Wp, nfb = dg.traces(W, 0, st)
+    assert nfb == 1
+    # element 1's - trace is its node 0 (the node nearest x = -1), bit for bit
+    assert torch.equal(Wm[:, 0, 0, 1, 0, 0], W[:, 0, 0, 1, 0, 0, 0])
+    r = np.sqrt(0.6)  # l_a(+1) on the nodes (-r, 0, r), written out from the product formula
+    lp = np.array([(1.0 - r) / 1.2, -2.0 / 3.0, (1.0 + r) / 1.2])
+    for k in range(st.nvar):
+        ref = float((torch.tensor(lp) * W[k, 0, 0, 1, 0, 0, :]).sum())
+        assert abs(float(Wp[k, 0, 0, 1, 0, 0]) - ref) <= 1e-15 * max(1.0, abs(ref))
+    assert float(Wp[0, 0, 0, 1, 0, 0]) > 0.5
+    # the other elements are uniform: their traces are the node states
+    assert torch.allclose(Wm[:, 0, 0, 0, 0, 0], W[:, 0, 0, 0, 0, 0, 1], rtol=1e-14, atol=0)
+
+
+def test_trace_fallback_pressure_2d_along_y():
+    """The same for the pressure on the + face along y of a p = 3 element: pressures
+    (1, 1, 1, 0.001) up one column interpolate to < 0 at y = +1 (l(+1) has weight
+    -0.81 on the third node and 1.53 on the fourth), so that face point takes the
+    primitives of the node nearest y = +1; the counter counts that one point."""
+    st = Setup(dim=2, p=3, n_elem=(2, 2, 1), eos=TM, bc=(PERIODIC, OUTFLOW, PERIODIC))
+    shape = st.shape()
+    rho = np.ones(shape)
+    P = np.ones(shape)
+    # element (ex=1, ey=0), column i = 2: nodes j = 0..3
+    P[0, 0, 1, 0, :, 2] = (1.0, 1.0, 1.0, 0.001)
+    v = np.zeros((2,) + shape)
+    v[0] = 0.1
+    U = _prims_from_nodes(st, rho, v, P)
+    W, _ = cp.con2prim(U, st)
+    Wm, Wp, nfb = dg.traces(W, 1, st)
+    assert nfb == 1
+    assert float(Wp[-1, 0, 0, 1, 0, 2]) == float(W[-1, 0, 0, 1, 0, 3, 2])
+    assert torch.equal(Wp[:, 0, 0, 1, 0, 2], W[:, 0, 0, 1, 0, 3, 2])
+    # the surface term counts the same fallback through its stats
+    stats = {}
+    dg.surface_term(W, st, stats)
+    assert stats["trace_fallbacks"] == 1
