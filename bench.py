@@ -9,7 +9,12 @@ Default workload: 2D relativistic Kelvin-Helmholtz, Taub-Matthews EOS,
 256x256 elements, p=3 (16 nodes per element, 1,048,576 DOF), FP64, HLL,
 physicality operator on.  Extra results on the same JSON line:
   fp32_contract  the 512x512 p=3 Kelvin-Helmholtz mesh in the FP32-contraction
-                 form vs the same mesh in FP64 (speedup on the same GPU);
+                 form vs the same mesh in FP64 (speedup on the same GPU), and the
+                 L1 error of both after 50 steps against the oracle's FP64 run;
+  wave1d         the 1D density wave (64 elements, p=2, 100 steps): L1 error of
+                 D against the exact translated solution, drift from the oracle;
+  random3d       the 3D stress field (64^3 p=2): step 1 from the initial state,
+                 then 20 steps with the failure fractions after each;
   adjoint        cost of the checkpointed adjoint of 200 steps (checkpoint every
                  20) relative to the forward run, 128x128 p=2 ideal-gas mesh;
   roofline       the stage kernel against HBM, from algorithmic bytes per
@@ -260,30 +265,108 @@ def con2prim_study(runs=100):
             "solvers": out}
 
 
-def other_configs():
-    """The remaining named workloads, timed as configured: the 3D stress field (64^3 p=2,
-    FP32 contractions, the physicality operator active) and the 1D density wave (64
-    elements, launch-bound, informational)."""
+def random3d_leg(repeats=5):
+    """The 3D stress field (64^3 p=2, FP32 contractions, the physicality operator active).
+
+    On this i.i.d. field most nodes fail recovery after the first stage and the state
+    turns non-finite within a few steps (the oracle's own run does the same), so a
+    multi-step rate measures the floor-state path, not the method.  Reported: step 1
+    timed from a fresh copy of the initial state (median of `repeats`), with its event
+    fractions; then the configured 20 steps one by one, with the fractions of failed
+    recoveries, inadmissible averages and non-finite nodes after each step, and their
+    rate labelled as failure-path throughput."""
+    import statistics
     import torch
     from paper_2205_00095_amd import workloads as wl
-    out = {}
-    for kind, warm in (("random3d", 2), ("wave1d", 10)):
-        cfg, solver, U = _setup(kind)
-        n = cfg["steps"]
+    cfg, solver, U0 = _setup("random3d")
+    dofs = wl.n_dof(cfg)
+    nel = dofs // (cfg["p"] + 1) ** cfg["dim"]
+    nvar = wl.n_var(cfg)
+    bpd = _stage_bytes_per_dof(nvar)
+    stream = torch.cuda.current_stream()
+    U = torch.empty_like(U0)
+    times = []
+    for _ in range(repeats + 1):
+        U.copy_(U0)
         solver.reset_diagnostics()
-        sec = _time_run(solver, U, cfg["dt"], n, warm)
-        d = solver.diagnostics()
-        dofs = wl.n_dof(cfg)
-        stages = 3 * (n + warm)
-        bpd = _stage_bytes_per_dof(wl.n_var(cfg))
-        out[kind] = {"dof": dofs, "steps": n, "dof_stage_per_s": dofs * n * 3 / sec, "stage_us": sec / (3 * n) * 1e6,
-                     "algorithmic_bytes_per_dof": bpd, "hbm_frac": bpd * dofs * n * 3 / sec / (HBM_PEAK_GBS * 1e9),
-                     "precision": "fp32-contraction" if cfg["precision"] == wl.FP32_CONTRACT else "fp64",
-                     "per_stage": {k: d[k] / stages for k in ("smoothed", "flagged", "trace_fallback", "c2p_fail",
-                                                            "bad_average")}}
-        solver.close()
-        del U
-    return out
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        solver.run(U, cfg["dt"], 1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    d1 = solver.diagnostics()
+    t1 = statistics.median(times[1:])
+
+    def fractions(d, stages):
+        nonfinite = int((~torch.isfinite(U)).any(0).sum())
+        return {"c2p_fail": d["c2p_fail"] / (dofs * stages), "bad_average": d["bad_average"] / (nel * stages),
+                "smoothed": d["smoothed"] / (nel * stages), "trace_fallback_per_stage": d["trace_fallback"] / stages,
+                "nonfinite_nodes": nonfinite / dofs}
+
+    step1 = {"us": t1 * 1e6, "dof_stage_per_s": dofs * 3 / t1,
+             "hbm_frac": bpd * dofs * 3 / t1 / (HBM_PEAK_GBS * 1e9), "fractions": fractions(d1, 3)}
+    U.copy_(U0)
+    per_step = []
+    total = 0.0
+    for k in range(cfg["steps"]):
+        solver.reset_diagnostics()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        solver.run(U, cfg["dt"], 1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1) / 1e3
+        per_step.append(fractions(solver.diagnostics(), 3))
+    n = cfg["steps"]
+    solver.close()
+    del U, U0
+    return {"workload": "random3d: 3D 64^3 elements p=2 ideal EOS, FP32 contractions, physicality operator on",
+            "dof": dofs, "algorithmic_bytes_per_dof": bpd,
+            "step1_from_initial_state": step1,
+            "failure_path_throughput": {
+                "steps": n, "dof_stage_per_s": dofs * n * 3 / total, "stage_us": total / (3 * n) * 1e6,
+                "hbm_frac": bpd * dofs * n * 3 / total / (HBM_PEAK_GBS * 1e9),
+                "note": "steps timed one by one after step 1 has driven most nodes to the floor state"},
+            "per_step_fractions": per_step,
+            "fraction_units": "c2p_fail per node-stage, bad_average and smoothed per element-stage, "
+                              "nonfinite_nodes after the step"}
+
+
+def wave1d_leg(steps=100):
+    """The 1D density wave (64 elements, p=2, ideal EOS): 100 SSP-RK3 steps at the fixed
+    step 0.1/(2p+1) dx/c; the L1 error of D against the exact translated solution, the
+    final state (for the drift against the oracle's run) and the launch-bound rate."""
+    import numpy as np
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    cfg, solver, U0 = _setup("wave1d")
+    U = U0.clone()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.run(U, cfg["dt"], steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    t = steps * cfg["dt"]
+    rho, v, _ = wl.wave1d_primitives(cfg, t)
+    D_exact = rho / np.sqrt(1.0 - (v[0] / cfg["c"]) ** 2)
+    _, w = np.polynomial.legendre.leggauss(cfg["p"] + 1)
+    h = (cfg["hi"][0] - cfg["lo"][0]) / cfg["n_elem"][0]
+    D = U[0].cpu().numpy()
+    l1 = float((0.5 * h * w * np.abs(D - D_exact)).sum())
+    dofs = wl.n_dof(cfg)
+    out = {"workload": "wave1d: 1D 64 elements p=2 ideal EOS, v = 0.5c density wave",
+           "steps": steps, "t_final": t, "l1_D_vs_exact": l1,
+           "dof_stage_per_s": dofs * steps * 3 / sec, "stage_us": sec / (3 * steps) * 1e6,
+           "note": "launch-bound (192 DOF); L1 = sum over nodes of (dx/2) w_q |D_h - D_exact|"}
+    final = U.cpu()
+    solver.close()
+    return out, final
 
 
 def paper_sweep(target_s=0.15):
@@ -356,21 +439,24 @@ def kh_growth(nx=256, orders=(0, 1, 2), t_end=3.0, sample_dt=0.05):
 
 def fp32_contract(steps=50):
     """The 512x512 p=3 Taub-Matthews mesh in the FP32-contraction form against the same
-    mesh in FP64 on the same GPU: throughputs, speedup, RHS error and solution drift."""
+    mesh in FP64 on the same GPU: throughputs, speedup and RHS error; also the two
+    solutions after `steps` steps from the initial state, for the L1 error against
+    the oracle's FP64 run of the same steps."""
     from paper_2205_00095_amd import workloads as wl
-    n3 = steps
     cfg3, s64, U64 = _setup("kh_tm_fp32", precision=wl.FP64)
     U0 = U64.clone()
     R64 = s64.rhs(U0)
-    t64 = _time_run(s64, U64, cfg3["dt"], n3, 5)
+    t64 = _time_run(s64, U64, cfg3["dt"], steps, 5)
     V64 = U0.clone()
-    s64.run(V64, cfg3["dt"], n3)
+    s64.run(V64, cfg3["dt"], steps)
+    s64.close()
     del s64, U64
     cfg3, s32, U32 = _setup("kh_tm_fp32")
     R32 = s32.rhs(U0)
-    t32 = _time_run(s32, U32, cfg3["dt"], n3, 5)
+    t32 = _time_run(s32, U32, cfg3["dt"], steps, 5)
     V32 = U0.clone()
-    s32.run(V32, cfg3["dt"], n3)
+    s32.run(V32, cfg3["dt"], steps)
+    s32.close()
     d3 = wl.n_dof(cfg3)
     nv3 = R64.shape[0]
     rhs_err = ((R32 - R64).reshape(nv3, -1).abs().max(1).values /
@@ -378,18 +464,35 @@ def fp32_contract(steps=50):
     drift = ((V32 - V64).reshape(nv3, -1).abs().sum(1) / V64.reshape(nv3, -1).abs().sum(1)).max().item()
     out = {
         "workload": "kh_tm_fp32: 2D 512x512 elements p=3 TM EOS",
-        "value_fp32": d3 * n3 * 3 / t32, "value_fp64": d3 * n3 * 3 / t64,
-        "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": n3,
-        "rhs_rel_err_vs_fp64": rhs_err, "l1_drift_vs_fp64_after_steps": drift,
-        "note": "errors against the FP64 GPU path on the same input (that path matches the FP64 oracle "
-                "to 1e-12 in the parity tests); max over conserved variables"}
+        "value_fp32": d3 * steps * 3 / t32, "value_fp64": d3 * steps * 3 / t64,
+        "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": steps,
+        "rhs_rel_err_vs_fp64_gpu": rhs_err, "l1_fp32_vs_fp64_gpu_after_steps": drift}
+    finals = {"fp32": V32.cpu(), "fp64": V64.cpu()}
     del s32, U32, R64, R32, V64, V32, U0
-    return out
+    return out, finals
+
+
+def _l1_rel(A, B):
+    """max over conserved components k of sum |A_k - B_k| / sum |B_k|."""
+    nv = B.shape[0]
+    return float(((A - B).reshape(nv, -1).abs().sum(1) / B.reshape(nv, -1).abs().sum(1)).max())
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(kind="kh_tm", steps=3, seconds=10.0):
     """The oracle as it stands, on the host cores: `steps` SSP-RK3 steps of the full mesh,
-    then as many more as fill about `seconds` of wall time in total (a bounded sample)."""
+    then as many more as fill about `seconds` of wall time in total (a bounded sample);
+    then one step on one thread."""
     import math
     import torch
     from oracle import srhd, timestep
@@ -399,20 +502,57 @@ def cpu_baseline(kind="kh_tm", steps=3, seconds=10.0):
     st = Setup.from_config(cfg)
     rho, v, P = (torch.from_numpy(a) for a in wl.initial_primitives(cfg))
     U = srhd.prim3_to_cons(rho, v, P, st).reshape((st.nvar,) + wl.field_shape(cfg))
+    threads = torch.get_num_threads()
     t0 = time.perf_counter()
-    U = timestep.run(U, cfg["dt"], steps, st)
+    U1 = timestep.run(U, cfg["dt"], steps, st)
     dt = time.perf_counter() - t0
     more = max(0, math.ceil((seconds - dt) / (dt / steps))) if steps > 0 else 0
     if more:
         t1 = time.perf_counter()
-        timestep.run(U, cfg["dt"], more, st)
+        timestep.run(U1, cfg["dt"], more, st)
         dt += time.perf_counter() - t1
         steps += more
     dofs = wl.n_dof(cfg)
-    return {"value": dofs * steps * 3 / dt, "unit": "DOF-stage/s", "cores": torch.get_num_threads(),
+    torch.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        timestep.run(U, cfg["dt"], 1, st)
+        dt1 = time.perf_counter() - t1
+    finally:
+        torch.set_num_threads(threads)
+    ref = _cpu_reference_runs()
+    rates = {k: {"dof_stage_per_s": wl.n_dof(wl.make_config(k)) * n * 3 / sec, "steps": n, "s": sec}
+             for k, (U_, sec, n) in ref.items()}
+    rec = {"value": dofs * steps * 3 / dt, "unit": "DOF-stage/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} SSP-RK3 steps of the full {cfg['n_elem'][0]}x{cfg['n_elem'][1]} p={cfg['p']} "
-                      f"mesh ({dofs} DOF), torch CPU float64, {dt:.1f} s"}
+                      f"mesh ({dofs} DOF), torch CPU float64 on {threads} threads, {dt:.1f} s",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+            "value_1_thread": dofs * 3 / dt1,
+            "sample_1_thread": f"1 SSP-RK3 step of the same mesh on 1 thread, {dt1:.1f} s",
+            "reference_runs": rates}
+    return rec, {k: v[0] for k, v in ref.items()}
+
+
+def _cpu_reference_runs(steps_c1=100, steps_c3=50):
+    """Part of the CPU baseline leg: the oracle's FP64 runs that the GPU results are
+    compared with: the 1D density
+    wave (100 steps) and the 512x512 p=3 TM Kelvin-Helmholtz mesh (50 steps), from the
+    same initial states as the GPU runs; returns the final states and the wall times."""
+    import torch
+    from oracle import srhd, timestep
+    from oracle.setup import Setup
+    from paper_2205_00095_amd import workloads as wl
+    out = {}
+    for kind, n in (("wave1d", steps_c1), ("kh_tm_fp32", steps_c3)):
+        cfg = wl.make_config(kind, precision=wl.FP64)
+        st = Setup.from_config(cfg)
+        rho, v, P = (torch.from_numpy(a) for a in wl.initial_primitives(cfg))
+        U = srhd.prim3_to_cons(rho, v, P, st).reshape((st.nvar,) + wl.field_shape(cfg))
+        t0 = time.perf_counter()
+        U = timestep.run(U, cfg["dt"], n, st)
+        out[kind] = (U, time.perf_counter() - t0, n)
+    return out
 
 
 def main(argv=None):
@@ -431,6 +571,8 @@ def main(argv=None):
                     help="only run the KH growth-rate diagnostic of the paper's Sec. 4 and print its JSON")
     ap.add_argument("--fp32-form", action="store_true",
                     help="only run the FP32-contraction comparison (512x512 p=3) and print its JSON")
+    ap.add_argument("--random3d", action="store_true",
+                    help="only run the 3D stress-field leg (64^3 p=2) and print its JSON")
     ap.add_argument("--adjoint", action="store_true",
                     help="only run the adjoint cost measurement (128x128 p=2, 200 steps) and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -452,7 +594,10 @@ def main(argv=None):
         print(json.dumps(kh_growth()), flush=True)
         return 0
     if args.fp32_form:
-        print(json.dumps(fp32_contract(min(args.steps, 50))), flush=True)
+        print(json.dumps(fp32_contract(50)[0]), flush=True)
+        return 0
+    if args.random3d:
+        print(json.dumps(random3d_leg()), flush=True)
         return 0
     if args.adjoint:
         print(json.dumps(adjoint_ratio()), flush=True)
@@ -529,13 +674,25 @@ def main(argv=None):
                     "f64_peak_frac": flops * dofs / stage_s / FP64_VECTOR_PEAK})
     if not args.no_extras and args.workload == "kh_tm":
         extras = {}
-        extras["fp32_contract"] = fp32_contract(min(args.steps, 50))
+        fp32, finals = fp32_contract(50)
+        extras["fp32_contract"] = fp32
         extras["hbm_copy_GBs"] = _copy_bandwidth() / 1e9
         extras["paper_sweep"] = paper_sweep()
-        extras["other_configs"] = other_configs()
+        extras["random3d"] = random3d_leg()
+        c1, c1_final = wave1d_leg(100)
+        extras["wave1d"] = c1
         extras["adjoint"] = adjoint_ratio()
         out.update(extras)
-        out["cpu_baseline"] = cpu_baseline("kh_tm", args.cpu_steps, args.cpu_seconds)
+        # the CPU leg also runs the oracle's FP64 runs of the 1D wave and of the 512x512
+        # mesh, against which the GPU results after the same steps are compared
+        out["cpu_baseline"], ref = cpu_baseline("kh_tm", args.cpu_steps, args.cpu_seconds)
+        out["wave1d"]["l1_gpu_vs_oracle"] = _l1_rel(c1_final, ref["wave1d"].reshape(c1_final.shape))
+        U_c3 = ref["kh_tm_fp32"].reshape(finals["fp32"].shape)
+        out["fp32_contract"]["l1_fp32_vs_oracle_fp64"] = _l1_rel(finals["fp32"], U_c3)
+        out["fp32_contract"]["l1_fp64_vs_oracle_fp64"] = _l1_rel(finals["fp64"], U_c3)
+        out["fp32_contract"]["note"] = ("L1 errors: max over conserved components of sum |U - U_ref| / sum |U_ref| "
+                                        "after the steps, against the oracle's FP64 run from the same initial "
+                                        "state (CPU) and against the GPU's FP64 path")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -74,8 +74,10 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * stage, three Newton steps on the same cubic started from the node's primitives
  * of the previous stage and accepted only when converged on the physical root,
  * else the CUBIC result; outside a stage the CUBIC result).  precision = DG_FP32_CONTRACT
- * evaluates the volume, trace and lift contractions in FP32 on deviations from
- * a per-element FP64 reference; everything else stays FP64.  phys = 1 applies
+ * evaluates the volume (D-hat) and lift contractions in FP32 with FP32
+ * accumulation, on deviations from an FP64 reference per line of nodes; the face
+ * traces, the recovery, the fluxes, the numerical flux, the operator and the RK
+ * combine stay FP64.  phys = 1 applies
  * the physicality-enforcing operator (Sec. 2.5) after every SSP-RK stage, with
  * relative margin phys_eps (0 selects 1e-12).  flux selects the numerical flux at
  * the faces (Sec. 2.4): DG_FLUX_HLL (0, the default when the field is zeroed) or
@@ -115,6 +117,10 @@ typedef struct {
  * host in FP64 and allocates scratch (about 5 states).  hip_stream may be NULL
  * (the null stream).  On failure *out is NULL and a negative code is returned. */
 int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out);
+/* Make hip_stream the context's stream for the calls that follow.  Every call on a
+ * context shares its scratch, so when the stream changes the new stream is made to
+ * wait (an event, no host synchronisation) for the work already queued on the old
+ * one; calls on the same context are thus ordered whatever streams they use. */
 int dg_set_stream(dg_ctx* ctx, void* hip_stream);
 
 /* Number of doubles in one nodal state array (n_var * n_elements * (p+1)^dim). */

@@ -10,6 +10,7 @@
 struct dg_ctx {
   dg_mesh_desc desc{};
   hipStream_t stream = nullptr;
+  hipEvent_t handoff = nullptr;      // orders a new stream after the work queued on the old one
   dgsrhd::PhysParams q{};
   dgsrhd::Tables t{};
   dgsrhd::MeshArgs m{};

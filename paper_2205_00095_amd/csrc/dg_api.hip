@@ -304,6 +304,7 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   if (e == hipSuccess) e = hipMalloc((void**)&c->U1, bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->U2, bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->cnt, sizeof(Counters) * kCounterSlots);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->handoff, hipEventDisableTiming);
   if (e != hipSuccess) {
     std::fprintf(stderr, "dg_init_mesh: allocation failed: %s\n", hipGetErrorString(e));
     dg_destroy(c);
@@ -322,9 +323,17 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   return DG_OK;
 }
 
+// Every call of a context shares its scratch (primitive and stage buffers, counters):
+// when the stream changes, the new one first waits for what is queued on the old one.
 int dg_set_stream(dg_ctx* c, void* hip_stream) {
   if (!c) return DG_EINVAL;
-  c->stream = (hipStream_t)hip_stream;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  if (s == c->stream) return DG_OK;
+  int r = hipcheck(c, hipEventRecord(c->handoff, c->stream), "dg_set_stream");
+  if (r) return r;
+  r = hipcheck(c, hipStreamWaitEvent(s, c->handoff, 0), "dg_set_stream");
+  if (r) return r;
+  c->stream = s;
   return DG_OK;
 }
 
@@ -482,6 +491,7 @@ void dg_destroy(dg_ctx* c) {
   (void)hipFree(c->U2);
   (void)hipFree(c->adj);
   (void)hipFree(c->cnt);
+  if (c->handoff) (void)hipEventDestroy(c->handoff);
   delete c;
 }
 

@@ -7,8 +7,9 @@ stress field (FP32 contractions, physicality operator on).  The oracle is
 vectorised, so it evaluates every output at these sizes.
 
 FP32-contraction bar: <= 1e-5 normwise relative per conserved component on the
-RHS (the volume, trace and lift contractions run in FP32 on deviations from an
-FP64 per-element reference; everything else is FP64)."""
+RHS (the volume and lift contractions run in FP32 with FP32 accumulation on
+deviations from an FP64 reference per line of nodes; the traces and everything
+else are FP64)."""
 import pytest
 import torch
 
