@@ -212,6 +212,26 @@ const char* dg_last_error(const dg_ctx* ctx);
 /* Release the context and its scratch (synchronises the stream first). */
 void dg_destroy(dg_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): dg_rhs without a context and
+ * without any allocation.  desc is validated and its tables are built on the host
+ * at every call (as dg_init_mesh would, DG_EINVAL when rejected); U_dev and R_dev
+ * are as in dg_rhs (caller-owned, [n_var][elements][nodes], not overlapping) and
+ * the result equals dg_rhs's bit for bit.  Scratch: a static device array of 64 MiB
+ * per GPU, held from the first call on that GPU until the process ends, holding the
+ * counters and the primitive staging; meshes whose state holds more than
+ * DG_RHS_NOALLOC_MAX_STATE doubles (n_var x elements x (p+1)^dim) are rejected with
+ * DG_EINVAL.  The work is enqueued on hip_stream, which must belong to the current
+ * device; the first call on each device resolves the array's address (make it
+ * outside a capture).  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (several streams or host threads) race.  The counters restart at zero
+ * at every call; with diag non-NULL, or desc->sync_mode = 1, the call synchronises
+ * hip_stream and reports them (not under capture), sync_mode also returning
+ * DG_ECON2PRIM after a recovery failure.  Messages go to stderr. */
+#define DG_RHS_NOALLOC_MAX_STATE 8380416u
+int dg_rhs_noalloc(const dg_mesh_desc* desc, void* hip_stream, const double* U_dev, double* R_dev,
+                   dg_diag* diag);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,11 @@ SIGNATURES = {
     "dg_reset_diagnostics": (_I, [_P]),
     "dg_last_error": (ctypes.c_char_p, [_P]),
     "dg_destroy": (None, [_P]),
+    "dg_rhs_noalloc": (_I, [ctypes.POINTER(MeshDesc), _P, _P, _P, ctypes.POINTER(Diag)]),
 }
+
+# primitive staging the allocation-free right-hand side holds (DG_RHS_NOALLOC_MAX_STATE)
+RHS_NOALLOC_MAX_STATE = 8380416
 
 _lib = None
 

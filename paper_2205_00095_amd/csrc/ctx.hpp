@@ -7,15 +7,21 @@
 #include "../../include/dgsrhd.h"
 #include "launch.hpp"
 
-struct dg_ctx {
+namespace dgsrhd {
+// A validated mesh description and what is derived from it on the host.
+struct MeshSetup {
   dg_mesh_desc desc{};
-  hipStream_t stream = nullptr;
-  hipEvent_t handoff = nullptr;      // orders a new stream after the work queued on the old one
-  dgsrhd::PhysParams q{};
-  dgsrhd::Tables t{};
-  dgsrhd::MeshArgs m{};
+  PhysParams q{};
+  Tables t{};
+  MeshArgs m{};
   int nv = 0, npe = 0;
   long long ntot = 0;
+};
+}  // namespace dgsrhd
+
+struct dg_ctx : dgsrhd::MeshSetup {
+  hipStream_t stream = nullptr;
+  hipEvent_t handoff = nullptr;      // orders a new stream after the work queued on the old one
   double* Wa = nullptr;
   double* Wb = nullptr;
   double* U1 = nullptr;
@@ -34,6 +40,9 @@ int fail(dg_ctx* c, int code, const char* fmt, ...);
 int hipcheck(dg_ctx* c, hipError_t e, const char* what);
 int finish(dg_ctx* c, const char* what);
 ElemArgs base_args(dg_ctx* c);
+const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s);
+hipError_t launch_element(const MeshSetup& s, int mode, const ElemArgs& a, hipStream_t st);
+hipError_t launch_con2prim(const MeshSetup& s, const double* U, double* W, Counters* cnt, hipStream_t st);
 hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a);
 hipError_t L_con2prim(dg_ctx* c, const double* U, double* W);
 hipError_t L_enforce(dg_ctx* c, double* U);

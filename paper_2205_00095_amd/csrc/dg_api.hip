@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -27,9 +28,9 @@ __global__ void k_reset_counters(Counters* cnt) {
 }
 
 // All slots summed (first_bad: the minimum); synchronous.
-static hipError_t read_counters(const dg_ctx* c, Counters& out) {
+static hipError_t read_counters(const Counters* dev, Counters& out) {
   Counters h[kCounterSlots];
-  hipError_t e = hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpy(h, dev, sizeof(h), hipMemcpyDeviceToHost);
   out = Counters{};
   out.first_bad = ~0ull;
   if (e != hipSuccess) return e;
@@ -44,6 +45,17 @@ static hipError_t read_counters(const dg_ctx* c, Counters& out) {
     out.first_bad = h[i].first_bad < out.first_bad ? h[i].first_bad : out.first_bad;
   }
   return hipSuccess;
+}
+
+static void to_diag(const Counters& h, dg_diag* out) {
+  out->c2p_fail = (long long)h.c2p_fail;
+  out->c2p_noconv = (long long)h.c2p_noconv;
+  out->trace_fallback = (long long)h.trace_fallback;
+  out->flagged = (long long)h.flagged;
+  out->smoothed = (long long)h.smoothed;
+  out->bad_average = (long long)h.bad_average;
+  out->bad_input = (long long)h.bad_input;
+  out->first_bad_elem = (h.first_bad == ~0ull) ? -1 : (long long)h.first_bad;
 }
 
 }  // namespace dgsrhd
@@ -70,10 +82,11 @@ int hipcheck(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 // Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n, and the
-// Lagrange tables through barycentric weights.
+// Lagrange tables through barycentric weights.  Fixed-size arrays (p <= 3): no
+// allocation, so the allocation-free entry point can build its tables per call.
 void gl_tables(int p, int dim, Tables& t) {
   const int n = p + 1;
-  std::vector<double> x(n), w(n);
+  double x[kMaxN1], w[kMaxN1];
   if (n == 1) {
     x[0] = 0.0;
     w[0] = 2.0;
@@ -105,20 +118,22 @@ void gl_tables(int p, int dim, Tables& t) {
     }
     if (n % 2 == 1) x[n / 2] = 0.0;
   }
-  std::vector<double> bw(n, 1.0);
-  for (int j = 0; j < n; ++j)
+  double bw[kMaxN1];
+  for (int j = 0; j < n; ++j) {
+    bw[j] = 1.0;
     for (int k = 0; k < n; ++k)
       if (k != j) bw[j] /= (x[j] - x[k]);
+  }
   // Dm[i][j] = l_j'(x_i)
-  std::vector<double> Dm(n * n, 0.0);
+  double Dm[kMaxN1][kMaxN1] = {};
   for (int i = 0; i < n; ++i) {
     double diag = 0.0;
     for (int j = 0; j < n; ++j) {
       if (j == i) continue;
-      Dm[i * n + j] = (bw[j] / bw[i]) / (x[i] - x[j]);
-      diag -= Dm[i * n + j];
+      Dm[i][j] = (bw[j] / bw[i]) / (x[i] - x[j]);
+      diag -= Dm[i][j];
     }
-    Dm[i * n + i] = diag;
+    Dm[i][i] = diag;
   }
   std::memset(&t, 0, sizeof(t));
   double wsum = 0.0;
@@ -134,7 +149,7 @@ void gl_tables(int p, int dim, Tables& t) {
     t.w[i] = w[i];
     t.iw[i] = 1.0 / w[i];
     wsum += w[i];
-    for (int a = 0; a < n; ++a) t.dhat[i][a] = w[a] * Dm[a * n + i] / w[i];
+    for (int a = 0; a < n; ++a) t.dhat[i][a] = w[a] * Dm[a][i] / w[i];
   }
   t.inv_wsum = 1.0 / std::pow(wsum, dim);
   for (int i = 0; i < n; ++i) {
@@ -145,23 +160,108 @@ void gl_tables(int p, int dim, Tables& t) {
   }
 }
 
+// Validate a mesh description and derive the physical parameters, basis tables and
+// mesh arguments from it, without allocating.  Returns null, or the reason the
+// description is rejected.
+const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s) {
+  s = MeshSetup{};
+  s.desc = *in;
+  dg_mesh_desc& d = s.desc;
+  if (d.dim < 1 || d.dim > 3) return "dim must be 1, 2 or 3";
+  if (d.p < 0 || d.p > 3) return "p must be in 0..3";
+  for (int k = 0; k < 3; ++k) {
+    if (k >= d.dim) d.n_elem[k] = 1;
+    if (d.n_elem[k] < 1) return "n_elem must be >= 1";
+    if (k < d.dim && !(d.hi[k] > d.lo[k])) return "hi must exceed lo";
+    if (d.bc[k] != DG_BC_PERIODIC && d.bc[k] != DG_BC_OUTFLOW && d.bc[k] != DG_BC_REFLECT &&
+        d.bc[k] != DG_BC_DIRICHLET)
+      return "bc must be periodic, outflow, reflect or dirichlet";
+    if (k >= d.dim) d.bc_hi[k] = 0;
+    if (d.bc_hi[k] != 0 && d.bc_hi[k] != DG_BC_OUTFLOW && d.bc_hi[k] != DG_BC_REFLECT &&
+        d.bc_hi[k] != DG_BC_DIRICHLET)
+      return "bc_hi must be 0, outflow, reflect or dirichlet";
+    if (d.bc[k] == DG_BC_PERIODIC && d.bc_hi[k] != 0) return "a periodic dimension has no separate upper end";
+  }
+  if (d.eos != DG_EOS_IDEAL && d.eos != DG_EOS_TM) return "unknown eos";
+  if (d.eos == DG_EOS_IDEAL && !(d.gamma_ad > 1.0)) return "gamma_ad must exceed 1";
+  if (!(d.c_light > 0.0)) return "c_light must be positive";
+  if (d.c2p == DG_C2P_DEFAULT) d.c2p = DG_C2P_NEWTON;
+  if (d.eos == DG_EOS_IDEAL && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_QUARTIC)
+    return "ideal EOS needs the Newton or quartic solver";
+  if (d.eos == DG_EOS_TM && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_CUBIC && d.c2p != DG_C2P_BRENT)
+    return "TM EOS needs the Newton, cubic or Brent solver";
+  if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT) return "unknown precision";
+  if (d.flux != DG_FLUX_HLL && d.flux != DG_FLUX_HLLC) return "flux must be HLL or HLLC";
+  if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
+  const long long nelem = (long long)d.n_elem[0] * d.n_elem[1] * d.n_elem[2];
+  if (nelem > (1ll << 30)) return "mesh too large";
+  s.nv = d.dim + 2;
+  s.npe = 1;
+  for (int k = 0; k < d.dim; ++k) s.npe *= d.p + 1;
+  s.ntot = nelem * s.npe;
+  PhysParams& q = s.q;
+  q.c = d.c_light;
+  q.c2 = q.c * q.c;
+  q.c4 = q.c2 * q.c2;
+  q.inv_c = 1.0 / q.c;
+  q.inv_c2 = 1.0 / q.c2;
+  q.gam = d.gamma_ad;
+  q.gm1 = d.gamma_ad - 1.0;
+  q.alpha = (d.eos == DG_EOS_IDEAL) ? d.gamma_ad / (d.gamma_ad - 1.0) : 0.0;
+  q.eps = d.phys_eps;
+  q.c2p = d.c2p;
+  gl_tables(d.p, d.dim, s.t);
+  MeshArgs& m = s.m;
+  m.nex = d.n_elem[0];
+  m.ney = d.n_elem[1];
+  m.nez = d.n_elem[2];
+  m.nelem = (int)nelem;
+  m.ntot = s.ntot;
+  for (int k = 0; k < 3; ++k) {
+    m.two_dx[k] = (k < d.dim) ? 2.0 * d.n_elem[k] / (d.hi[k] - d.lo[k]) : 0.0;
+    m.periodic[k] = (d.bc[k] == DG_BC_PERIODIC) ? 1 : 0;
+    m.bclo[k] = d.bc[k];
+    m.bchi[k] = d.bc_hi[k] != 0 ? d.bc_hi[k] : d.bc[k];
+    for (int end = 0; end < 2; ++end) {
+      const double* w = d.bc_state[k][end];
+      for (int i = 0; i < 5; ++i) m.bw[k][end][i] = 0.0;
+      if ((end == 0 ? m.bclo[k] : m.bchi[k]) != DG_BC_DIRICHLET || k >= d.dim) continue;
+      double v2 = 0.0;
+      for (int j = 0; j < d.dim; ++j) v2 += w[1 + j] * w[1 + j];
+      if (!(w[0] > 0.0) || !(w[4] > 0.0) || !(v2 < d.c_light * d.c_light))
+        return "a dirichlet end needs rho > 0, P > 0 and |v| < c";
+      const double g = 1.0 / std::sqrt(1.0 - v2 / (d.c_light * d.c_light));
+      m.bw[k][end][0] = w[0];
+      for (int j = 0; j < d.dim; ++j) m.bw[k][end][1 + j] = g * w[1 + j];
+      m.bw[k][end][4] = w[4];
+    }
+  }
+  return nullptr;
+}
+
+hipError_t launch_element(const MeshSetup& s, int mode, const ElemArgs& a, hipStream_t st) {
+  const int dim = s.desc.dim, p = s.desc.p, eos = s.desc.eos, prec = s.desc.precision, fl = s.desc.flux;
+  if (dim == 1) return launch_element_dim1(p, eos, prec, mode, fl, a, st);
+  if (dim == 2) return launch_element_dim2(p, eos, prec, mode, fl, a, st);
+  return launch_element_dim3(p, eos, prec, mode, fl, a, st);
+}
+
+hipError_t launch_con2prim(const MeshSetup& s, const double* U, double* W, Counters* cnt, hipStream_t st) {
+  const int dim = s.desc.dim, eos = s.desc.eos;
+  if (dim == 1) return launch_con2prim_dim1(eos, U, W, s.ntot, s.npe, s.q, cnt, st);
+  if (dim == 2) return launch_con2prim_dim2(eos, U, W, s.ntot, s.npe, s.q, cnt, st);
+  return launch_con2prim_dim3(eos, U, W, s.ntot, s.npe, s.q, cnt, st);
+}
+
 hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a0) {
-  const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos, prec = c->desc.precision, fl = c->desc.flux;
   // consecutive launches walk the tiles in opposite directions (cache reuse)
   ElemArgs a = a0;
   c->flip ^= 1;
   a.rev = c->flip;
-  if (dim == 1) return launch_element_dim1(p, eos, prec, mode, fl, a, c->stream);
-  if (dim == 2) return launch_element_dim2(p, eos, prec, mode, fl, a, c->stream);
-  return launch_element_dim3(p, eos, prec, mode, fl, a, c->stream);
+  return launch_element(*c, mode, a, c->stream);
 }
 
-hipError_t L_con2prim(dg_ctx* c, const double* U, double* W) {
-  const int dim = c->desc.dim, eos = c->desc.eos;
-  if (dim == 1) return launch_con2prim_dim1(eos, U, W, c->ntot, c->npe, c->q, c->cnt, c->stream);
-  if (dim == 2) return launch_con2prim_dim2(eos, U, W, c->ntot, c->npe, c->q, c->cnt, c->stream);
-  return launch_con2prim_dim3(eos, U, W, c->ntot, c->npe, c->q, c->cnt, c->stream);
-}
+hipError_t L_con2prim(dg_ctx* c, const double* U, double* W) { return launch_con2prim(*c, U, W, c->cnt, c->stream); }
 
 hipError_t L_enforce(dg_ctx* c, double* U) {
   const int dim = c->desc.dim, p = c->desc.p;
@@ -195,7 +295,7 @@ int finish(dg_ctx* c, const char* what) {
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
   Counters now{};
-  e = read_counters(c, now);
+  e = read_counters(c->cnt, now);
   if (e != hipSuccess) return fail(c, DG_EHIP, "%s: %s", what, hipGetErrorString(e));
   const Counters prev = c->last;
   c->last = now;
@@ -220,83 +320,13 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   if (!desc) return DG_EINVAL;
   dg_ctx* c = new (std::nothrow) dg_ctx();
   if (!c) return DG_ENOMEM;
-  c->desc = *desc;
-  dg_mesh_desc& d = c->desc;
-  auto bad = [&](const char* msg) {
-    std::fprintf(stderr, "dg_init_mesh: %s\n", msg);
+  const char* why = setup_mesh(desc, *c);
+  if (why) {
+    std::fprintf(stderr, "dg_init_mesh: %s\n", why);
     delete c;
     return DG_EINVAL;
-  };
-  if (d.dim < 1 || d.dim > 3) return bad("dim must be 1, 2 or 3");
-  if (d.p < 0 || d.p > 3) return bad("p must be in 0..3");
-  for (int k = 0; k < 3; ++k) {
-    if (k >= d.dim) d.n_elem[k] = 1;
-    if (d.n_elem[k] < 1) return bad("n_elem must be >= 1");
-    if (k < d.dim && !(d.hi[k] > d.lo[k])) return bad("hi must exceed lo");
-    if (d.bc[k] != DG_BC_PERIODIC && d.bc[k] != DG_BC_OUTFLOW && d.bc[k] != DG_BC_REFLECT &&
-        d.bc[k] != DG_BC_DIRICHLET)
-      return bad("bc must be periodic, outflow, reflect or dirichlet");
-    if (k >= d.dim) d.bc_hi[k] = 0;
-    if (d.bc_hi[k] != 0 && d.bc_hi[k] != DG_BC_OUTFLOW && d.bc_hi[k] != DG_BC_REFLECT &&
-        d.bc_hi[k] != DG_BC_DIRICHLET)
-      return bad("bc_hi must be 0, outflow, reflect or dirichlet");
-    if (d.bc[k] == DG_BC_PERIODIC && d.bc_hi[k] != 0) return bad("a periodic dimension has no separate upper end");
   }
-  if (d.eos != DG_EOS_IDEAL && d.eos != DG_EOS_TM) return bad("unknown eos");
-  if (d.eos == DG_EOS_IDEAL && !(d.gamma_ad > 1.0)) return bad("gamma_ad must exceed 1");
-  if (!(d.c_light > 0.0)) return bad("c_light must be positive");
-  if (d.c2p == DG_C2P_DEFAULT) d.c2p = DG_C2P_NEWTON;
-  if (d.eos == DG_EOS_IDEAL && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_QUARTIC)
-    return bad("ideal EOS needs the Newton or quartic solver");
-  if (d.eos == DG_EOS_TM && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_CUBIC && d.c2p != DG_C2P_BRENT)
-    return bad("TM EOS needs the Newton, cubic or Brent solver");
-  if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT) return bad("unknown precision");
-  if (d.flux != DG_FLUX_HLL && d.flux != DG_FLUX_HLLC) return bad("flux must be HLL or HLLC");
-  if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
-  const long long nelem = (long long)d.n_elem[0] * d.n_elem[1] * d.n_elem[2];
-  if (nelem > (1ll << 30)) return bad("mesh too large");
   c->stream = (hipStream_t)hip_stream;
-  c->nv = d.dim + 2;
-  c->npe = 1;
-  for (int k = 0; k < d.dim; ++k) c->npe *= d.p + 1;
-  c->ntot = nelem * c->npe;
-  PhysParams& q = c->q;
-  q.c = d.c_light;
-  q.c2 = q.c * q.c;
-  q.c4 = q.c2 * q.c2;
-  q.inv_c = 1.0 / q.c;
-  q.inv_c2 = 1.0 / q.c2;
-  q.gam = d.gamma_ad;
-  q.gm1 = d.gamma_ad - 1.0;
-  q.alpha = (d.eos == DG_EOS_IDEAL) ? d.gamma_ad / (d.gamma_ad - 1.0) : 0.0;
-  q.eps = d.phys_eps;
-  q.c2p = d.c2p;
-  gl_tables(d.p, d.dim, c->t);
-  MeshArgs& m = c->m;
-  m.nex = d.n_elem[0];
-  m.ney = d.n_elem[1];
-  m.nez = d.n_elem[2];
-  m.nelem = (int)nelem;
-  m.ntot = c->ntot;
-  for (int k = 0; k < 3; ++k) {
-    m.two_dx[k] = (k < d.dim) ? 2.0 * d.n_elem[k] / (d.hi[k] - d.lo[k]) : 0.0;
-    m.periodic[k] = (d.bc[k] == DG_BC_PERIODIC) ? 1 : 0;
-    m.bclo[k] = d.bc[k];
-    m.bchi[k] = d.bc_hi[k] != 0 ? d.bc_hi[k] : d.bc[k];
-    for (int end = 0; end < 2; ++end) {
-      const double* w = d.bc_state[k][end];
-      for (int i = 0; i < 5; ++i) m.bw[k][end][i] = 0.0;
-      if ((end == 0 ? m.bclo[k] : m.bchi[k]) != DG_BC_DIRICHLET || k >= d.dim) continue;
-      double v2 = 0.0;
-      for (int j = 0; j < d.dim; ++j) v2 += w[1 + j] * w[1 + j];
-      if (!(w[0] > 0.0) || !(w[4] > 0.0) || !(v2 < d.c_light * d.c_light))
-        return bad("a dirichlet end needs rho > 0, P > 0 and |v| < c");
-      const double g = 1.0 / std::sqrt(1.0 - v2 / (d.c_light * d.c_light));
-      m.bw[k][end][0] = w[0];
-      for (int j = 0; j < d.dim; ++j) m.bw[k][end][1 + j] = g * w[1 + j];
-      m.bw[k][end][4] = w[4];
-    }
-  }
   const size_t bytes = sizeof(double) * (size_t)c->nv * (size_t)c->ntot;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMalloc((void**)&c->Wa, bytes);
@@ -457,16 +487,9 @@ int dg_get_diagnostics(dg_ctx* c, dg_diag* out) {
   int r = hipcheck(c, hipStreamSynchronize(c->stream), "dg_get_diagnostics");
   if (r) return r;
   Counters h{};
-  r = hipcheck(c, read_counters(c, h), "dg_get_diagnostics");
+  r = hipcheck(c, read_counters(c->cnt, h), "dg_get_diagnostics");
   if (r) return r;
-  out->c2p_fail = (long long)h.c2p_fail;
-  out->c2p_noconv = (long long)h.c2p_noconv;
-  out->trace_fallback = (long long)h.trace_fallback;
-  out->flagged = (long long)h.flagged;
-  out->smoothed = (long long)h.smoothed;
-  out->bad_average = (long long)h.bad_average;
-  out->bad_input = (long long)h.bad_input;
-  out->first_bad_elem = (h.first_bad == ~0ull) ? -1 : (long long)h.first_bad;
+  to_diag(h, out);
   return DG_OK;
 }
 
@@ -496,3 +519,97 @@ void dg_destroy(dg_ctx* c) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ dg_rhs_noalloc
+// Device scratch of the allocation-free right-hand side: the counter slots at offset
+// 0, the primitive staging buffer from kNoAllocWOffset.  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code the array's name is only a
+// host-side stand-in: kernels and copies take the device address resolved per device
+// by hipGetSymbolAddress (noalloc_scratch), never the name itself.
+constexpr size_t kNoAllocBytes = 64ull << 20;
+constexpr size_t kNoAllocWOffset = 64ull << 10;
+static_assert(sizeof(dgsrhd::Counters) * dgsrhd::kCounterSlots <= kNoAllocWOffset, "counters fit before W");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kNoAllocMaxDevices = 64;
+void* g_noalloc_ptr[kNoAllocMaxDevices];
+std::mutex g_noalloc_mu;
+
+// Device address of `scratch` on the current device, resolved on the first call on
+// that device (with it current) and kept.
+hipError_t noalloc_scratch(unsigned char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_noalloc_ptr[dev]);
+  return hipSuccess;
+}
+
+int noalloc_fail(int code, const char* fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "dg_rhs_noalloc: %s\n", buf);
+  return code;
+}
+}  // namespace
+
+static_assert(DG_RHS_NOALLOC_MAX_STATE == (kNoAllocBytes - kNoAllocWOffset) / sizeof(double),
+              "the header's limit is the staging part of the scratch");
+
+extern "C" int dg_rhs_noalloc(const dg_mesh_desc* desc, void* hip_stream, const double* U, double* R,
+                              dg_diag* diag) {
+  if (!desc) return noalloc_fail(DG_EINVAL, "null description");
+  MeshSetup s;
+  const char* why = setup_mesh(desc, s);
+  if (why) return noalloc_fail(DG_EINVAL, "%s", why);
+  if (!U || !R) return noalloc_fail(DG_EINVAL, "null pointer");
+  if (U == R) return noalloc_fail(DG_EINVAL, "U and R alias");
+  const size_t need = (size_t)s.nv * (size_t)s.ntot;
+  if (need > (size_t)DG_RHS_NOALLOC_MAX_STATE)
+    return noalloc_fail(DG_EINVAL, "the mesh needs %zu doubles of primitive staging; the static scratch holds %zu",
+                        need, (size_t)DG_RHS_NOALLOC_MAX_STATE);
+  unsigned char* base = nullptr;
+  hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return noalloc_fail(DG_EHIP, "scratch address: %s", hipGetErrorString(e));
+  Counters* cnt = reinterpret_cast<Counters*>(base);
+  double* W = reinterpret_cast<double*>(base + kNoAllocWOffset);
+  const hipStream_t st = (hipStream_t)hip_stream;
+  // the counters start at zero on every call (a kernel, not a memset node)
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = launch_con2prim(s, U, W, cnt, st);
+  if (e == hipSuccess) {
+    ElemArgs a{};
+    a.m = s.m;
+    a.t = s.t;
+    a.q = s.q;
+    a.cnt = cnt;
+    a.phys = s.desc.phys;
+    a.W = W;
+    a.out = R;
+    e = launch_element(s, MODE_RHS, a, st);
+  }
+  if (e != hipSuccess) return noalloc_fail(DG_EHIP, "launch: %s", hipGetErrorString(e));
+  if (!diag && !s.desc.sync_mode) return DG_OK;
+  e = hipStreamSynchronize(st);
+  Counters h{};
+  if (e == hipSuccess) e = read_counters(cnt, h);
+  if (e != hipSuccess) return noalloc_fail(DG_EHIP, "counters: %s", hipGetErrorString(e));
+  if (diag) to_diag(h, diag);
+  if (s.desc.sync_mode && h.c2p_fail > 0)
+    return noalloc_fail(DG_ECON2PRIM, "%llu recovery failures (first element %llu)", h.c2p_fail, h.first_bad);
+  return DG_OK;
+}

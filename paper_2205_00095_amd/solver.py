@@ -234,3 +234,30 @@ def primitives_tensor(rho, v, P, device="cuda") -> torch.Tensor:
     import numpy as np
     arr = np.concatenate([rho[None], v, P[None]], axis=0)
     return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float64)).to(device)
+
+
+def rhs_noalloc(cfg: dict, U: torch.Tensor, R: torch.Tensor, diag: bool = False, sync: bool = False):
+    """dg_rhs through the allocation-free entry point (no context, static device scratch).
+
+    R must be preallocated by the caller; with diag=True the call synchronises and
+    returns the counters of this call as a dict, else None."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("dgsrhd needs a ROCm GPU (torch.cuda.is_available() is False)")
+    lib = _lib.load()
+    shape = (cfg["dim"] + 2,) + field_shape(cfg)
+    numel = 1
+    for s in shape:
+        numel *= s
+    for name, t in (("U", U), ("R", R)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 GPU tensor")
+        if t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    desc = _desc_from_config(cfg, sync)
+    d = _lib.Diag() if diag else None
+    rc = lib.dg_rhs_noalloc(ctypes.byref(desc), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                            ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(R.data_ptr()),
+                            ctypes.byref(d) if diag else None)
+    if rc != 0:
+        raise _lib.DGError(rc, "dg_rhs_noalloc", "see stderr")
+    return {name: getattr(d, name) for name, _ in _lib.Diag._fields_} if diag else None

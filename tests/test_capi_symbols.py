@@ -79,3 +79,30 @@ def test_invalid_descriptions_are_rejected_without_a_gpu(change):
     out = ctypes.c_void_p()
     assert lib.dg_init_mesh(ctypes.byref(d), None, ctypes.byref(out)) == _lib.DG_EINVAL
     assert not out.value
+
+
+def test_noalloc_rejections_happen_on_the_host():
+    """dg_rhs_noalloc validates the description, the pointers and the mesh size against its
+    static scratch before any device call (fake pointers are never dereferenced)."""
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2205_00095_amd import _lib
+    lib = _lib.load()
+    fake_u, fake_r = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert lib.dg_rhs_noalloc(None, None, fake_u, fake_r, None) == _lib.DG_EINVAL
+    d = _desc()
+    assert lib.dg_rhs_noalloc(ctypes.byref(d), None, None, fake_r, None) == _lib.DG_EINVAL
+    assert lib.dg_rhs_noalloc(ctypes.byref(d), None, fake_u, fake_u, None) == _lib.DG_EINVAL
+    bad = _desc(p=5)
+    assert lib.dg_rhs_noalloc(ctypes.byref(bad), None, fake_u, fake_r, None) == _lib.DG_EINVAL
+    # 1D p=2: 3 variables x 3 nodes per element; one element more than the scratch holds
+    n_fit = _lib.RHS_NOALLOC_MAX_STATE // 9
+    big = _desc(n_elem=(n_fit + 1, 1, 1))
+    assert lib.dg_rhs_noalloc(ctypes.byref(big), None, fake_u, fake_r, None) == _lib.DG_EINVAL
+
+
+def test_noalloc_limit_matches_the_header():
+    from paper_2205_00095_amd import _lib
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+DG_RHS_NOALLOC_MAX_STATE\s+(\d+)u", text)
+    assert m and int(m.group(1)) == _lib.RHS_NOALLOC_MAX_STATE
