@@ -30,13 +30,60 @@ def perturbed(U, rel=1e-15, seed=0):
     return U * (1.0 + rel * torch.randn(U.shape, generator=g, dtype=torch.float64))
 
 
-def parity_tol(fn, U, floor=1e-12):
-    """Acceptance bar for GPU-vs-oracle parity of X = fn(U): 1e-12 normwise relative per
-    component, or 4x the oracle's own response to ~5-ulp relative perturbations of its
-    input (max over two seeds) when the problem's FP64 conditioning makes that larger
-    (cancellation-dominated RHS, chaotic stress data).  Returns (tol, sensitivity)."""
-    X0 = fn(U)
-    sens = torch.maximum(rel_err_per_var(fn(perturbed(U, seed=0)), X0),
-                         rel_err_per_var(fn(perturbed(U, seed=1)), X0))
-    # one or two random perturbations under-sample the worst case: allow 4x
-    return torch.clamp(4.0 * sens, min=floor), sens
+# Fixed bars of the cases whose map amplifies rounding beyond its cancellation ratio: the
+# random 3D stress field (Lorentz factors to 20, densities varying by 1e6 between
+# neighbouring nodes, the physicality operator acting on most elements) and a step 300
+# times the stable one.  There the oracle itself moves by the amount quoted when its
+# input moves by one ulp (relative N(0, 2e-32) perturbations, six seeds), so no FP64
+# evaluation can agree more closely; each bar is a fixed multiple (>= 3) of that.
+AMPLIFIED_BARS = {
+    "random3d 5x4x3 p=2 1 step": 1e-8,        # 1-ulp sensitivity 1.2e-9 .. 2.7e-9
+    "random3d 4x3x3 p=1 SSPRK2 1 step": 5e-8,  # 4.1e-9 .. 1.2e-8
+    "random3d 4x1x3 p=3 2 steps": 1e-9,        # 3.9e-11 .. 1.6e-10
+    "kh_tm 9x8 p=3 dt x300 1 step": 3e-11,     # 6.0e-12 .. 8.4e-12
+    "riemann2d test 1 16x16 p=1 step": 1e-11,  # 2.7e-13 .. 2.6e-12 per step from the oracle's state
+}
+
+# Parity bars.  Two correct FP64 evaluations of the DG operator differ by a modest
+# multiple of u kappa, u = 2^-53 and kappa the cancellation ratio of what is compared
+# (tests/_conditioning.py); C_ROUND is that multiple: measured GPU-vs-oracle ratios stay
+# below 16 on every smooth case (the largest at 512x512 p=3), so 32 leaves a factor 2.
+# Bars never go below the 1e-12 normwise relative per component that the method's
+# FP64 path is held to.
+C_ROUND = 32.0
+FLOOR = 1e-12
+
+
+def rhs_bar(U, st, R_ref):
+    """(bar, kappa) per conserved component for R = dg.rhs(U): max(1e-12, C_ROUND u kappa)."""
+    from ._conditioning import U_ROUND, rhs_cancellation
+    kappa = rhs_cancellation(U, st, R_ref)
+    return torch.clamp(C_ROUND * U_ROUND * kappa, min=FLOOR), kappa
+
+
+def step_bar(U, dt, nsteps, st, order=3, phys=True, stats=None):
+    """(U_ref, bar, kappa) for nsteps SSP-RK steps of the oracle from U.
+
+    Each stage forms a combination of states and dt times the RHS, so its rounding is
+    bounded by u times (the state's magnitude + dt times the RHS term magnitude T):
+    kappa_k = sum over stages of (||U^(s)_k|| + dt ||T_k(U^(s))||) / ||U_out,k||."""
+    from oracle import dg as odg
+    from oracle import physicality as ophys
+    from oracle import timestep as ots
+    from ._conditioning import U_ROUND, rhs_term_magnitude
+    nv = U.shape[0]
+    acc = torch.zeros(nv, dtype=torch.float64)
+
+    def norm(X):
+        return X.reshape(nv, -1).abs().max(1).values
+
+    def L(V):
+        acc.add_(norm(V) + dt * norm(rhs_term_magnitude(V, st)))
+        return odg.rhs(V, st, stats)
+
+    Pi = (lambda V: ophys.enforce(V, st, stats)) if phys else (lambda V: V)
+    X = U
+    for _ in range(nsteps):
+        X = ots.SCHEMES[order](X, dt, L, Pi)
+    kappa = acc / norm(X).clamp(min=1e-300)
+    return X, torch.clamp(C_ROUND * U_ROUND * kappa, min=FLOOR), kappa

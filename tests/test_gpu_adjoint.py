@@ -203,10 +203,40 @@ def test_trajectory_gradient_matches_oracle():
     assert float(err.max()) <= 1e-9
 
 
+def test_trajectory_gradient_two_segments_matches_oracle():
+    """dJ/d(v_y perturbation) through 40 steps of a 16x16 p=2 ideal-gas KH mesh with a
+    checkpoint every 20 steps (two recomputed segments, as in the adjoint workload)
+    against the oracle's reverse mode, to 1e-6 normwise relative."""
+    from paper_2205_00095_amd.adjoint import vy2_after
+    cfg = wl.make_config("kh_ideal", n_elem=(16, 16, 1))
+    st = Setup.from_config(cfg)
+    rho, v, P = wl.initial_primitives(cfg)
+    v = v.copy()
+    v[1] += wl.kh_perturbation(cfg)
+    src = torch.from_numpy(wl.pack_primitives(rho, v, P))
+    dt, nsteps = cfg["dt"], 40
+    s_r = src.clone().requires_grad_(True)
+    U = osrhd.prim3_to_cons(s_r[0], s_r[1:3], s_r[3], st)
+    Jref = oobj.vy2_integral(ots.run(U, dt, nsteps, st), st)
+    (gref,) = torch.autograd.grad(Jref, s_r)
+    sd = src.cuda().requires_grad_(True)
+    J = vy2_after(_solver(cfg), sd, nsteps, dt, k=20)
+    J.backward()
+    Jerr = abs(float(J) - float(Jref)) / abs(float(Jref))
+    err = rel_err_per_var(sd.grad.cpu(), gref)
+    print(f"J err {Jerr:.2e}; gradient err per primitive {err.tolist()}", flush=True)
+    assert Jerr <= 1e-12
+    assert float(err.max()) <= 1e-6, err.tolist()
+
+
 def test_trajectory_gradient_fd_kh_adjoint_workload():
     """The adjoint workload (128x128 p=2 ideal KH, 200 steps, checkpoint every 20):
     gradient w.r.t. the initial v_y perturbation vs central differences on 16 seeded
-    unit directions."""
+    unit directions v.  Each directional derivative <g, v> is judged against its own
+    size, |FD - <g, v>| <= 1e-6 |<g, v>|, at one step h = 1e-4 |delta| fixed for every
+    direction (the sweep over h is printed).  A direction nearly orthogonal to the
+    gradient (|<g, v>| < 1e-3 |g|) has no meaningful relative error; it is reported on
+    its own line and held to the absolute |FD - <g, v>| <= 1e-9 |g|."""
     from paper_2205_00095_amd.adjoint import vy2_after
     cfg = wl.make_config("kh_ideal")
     rho, v, P = wl.initial_primitives(cfg)
@@ -229,19 +259,28 @@ def test_trajectory_gradient_fd_kh_adjoint_workload():
     J.backward()
     g = src.grad[2]
     dirs = torch.from_numpy(wl.random_directions(cfg, 16)).cuda()
-    worst = 0.0
     gnorm = float(g.norm())
+    H = (1e-3, 1e-4, 1e-5, 1e-6)
+    worst_rel, worst_orth, n_orth = 0.0, 0.0, 0
     for k in range(16):
         ad = float((g * dirs[k]).sum())
-        # a direction almost orthogonal to the gradient is measured against 1e-3 |g|
-        scale = max(abs(ad), 1e-3 * gnorm)
-        errs = []
-        for hr in (1e-3, 1e-4, 1e-5, 1e-6):
+        diffs = []
+        for hr in H:
             h = hr * float(d0.norm())
             fd = (J_of(d0 + h * dirs[k]) - J_of(d0 - h * dirs[k])) / (2 * h)
-            errs.append(abs(fd - ad) / scale)
-        print(f"direction {k}: <g,v>/|g| = {ad / float(g.norm()):.3e}; FD relative errors "
-              f"(h = 1e-3 .. 1e-6 |delta|) {errs}", flush=True)
-        worst = max(worst, min(errs))
-    print(f"KH adjoint workload: max over 16 directions of the best-step FD error {worst:.3e}", flush=True)
-    assert worst <= 1e-6
+            diffs.append(abs(fd - ad))
+        at_h = diffs[H.index(1e-4)]
+        if abs(ad) >= 1e-3 * gnorm:
+            rel = at_h / abs(ad)
+            worst_rel = max(worst_rel, rel)
+            print(f"direction {k}: <g,v>/|g| = {ad / gnorm:.3e}; |FD - <g,v>| / |<g,v>| at h = 1e-3 .. 1e-6 "
+                  f"|delta|: {[d / abs(ad) for d in diffs]}", flush=True)
+        else:
+            n_orth += 1
+            worst_orth = max(worst_orth, at_h / gnorm)
+            print(f"direction {k} (nearly orthogonal): <g,v>/|g| = {ad / gnorm:.3e}; |FD - <g,v>| / |g| at "
+                  f"h = 1e-3 .. 1e-6 |delta|: {[d / gnorm for d in diffs]}", flush=True)
+    print(f"KH adjoint workload: worst relative FD error {worst_rel:.3e} over {16 - n_orth} directions; "
+          f"{n_orth} nearly orthogonal, worst |FD - <g,v>| / |g| {worst_orth:.3e}", flush=True)
+    assert worst_rel <= 1e-6
+    assert worst_orth <= 1e-9

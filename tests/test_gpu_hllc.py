@@ -10,7 +10,7 @@ from oracle import dg as odg
 from oracle import timestep as ots
 from paper_2205_00095_amd import workloads as wl
 
-from ._util import oracle_state, parity_tol, rel_err_per_var
+from ._util import oracle_state, rel_err_per_var, rhs_bar, step_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -42,12 +42,12 @@ def test_hllc_rhs_matches_oracle(kind, over):
     print(f"case hllc rhs {kind} {over}", flush=True)
     st, U = oracle_state(cfg)
     R_ref = odg.rhs(U, st)
-    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    bar, kappa = rhs_bar(U, st, R_ref)
     s = _solver(cfg)
     R = s.rhs(U.cuda()).cpu()
     err = rel_err_per_var(R, R_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
 
 
 @pytest.mark.parametrize("kind,over,nsteps,order", [("kh_tm", {"n_elem": (12, 10, 1)}, 4, 3),
@@ -57,14 +57,13 @@ def test_hllc_steps_match_oracle(kind, over, nsteps, order):
     cfg = _cfg(kind, over)
     print(f"case hllc steps {kind} {over} x{nsteps} order {order}", flush=True)
     st, U = oracle_state(cfg)
-    U_ref = ots.run(U, cfg["dt"], nsteps, st, phys=True, order=order)
-    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], nsteps, st, phys=True, order=order), U)
+    U_ref, bar, kappa = step_bar(U, cfg["dt"], nsteps, st, order=order)
     s = _solver(cfg, sync=False)
     Ud = U.cuda().contiguous()
     s.run(Ud, cfg["dt"], nsteps, order=order)
     err = rel_err_per_var(Ud.cpu(), U_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
 
 
 def test_hllc_fp32_form_within_bound():
@@ -173,11 +172,11 @@ def test_hllc_fullsize_rhs():
     print(f"case hllc fullsize {cfg['n_elem']}", flush=True)
     st, U = oracle_state(cfg)
     R_ref = odg.rhs(U, st)
-    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    bar, kappa = rhs_bar(U, st, R_ref)
     R = _solver(cfg, sync=False).rhs(U.cuda()).cpu()
     err = rel_err_per_var(R, R_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
 
 
 def test_hllc_trajectory_gradient_matches_oracle():

@@ -2,14 +2,19 @@
 
 Inputs are the seeded workloads converted by the oracle's own prim->cons, so
 both sides see the same U.  Acceptance per conserved component k:
-||X_gpu,k - X_oracle,k||_inf / ||X_oracle,k||_inf <= max(1e-12, 4 s_k), where s_k
-is the oracle's own normwise change when its input is perturbed by ~5 ulps
-(max over two seeds, tests/_util.parity_tol).  s_k < 1e-12 for the Kelvin-Helmholtz and 3D RHS
-cases, so the bar there is the plain 1e-12; it exceeds 1e-12 only where FP64
-conditioning forbids 1e-12 for any two roundings (the uniform-pressure contact
-wave, whose flux-divergence terms are ~1e3 x its RHS, and a full step on the
-random 3D stress data).  Meshes span several workgroups and end in a partial
-one (ragged tail)."""
+||X_gpu,k - X_oracle,k||_inf / ||X_oracle,k||_inf <= bar_k with
+  RHS:   bar_k = max(1e-12, 32 u kappa_k), kappa_k the cancellation ratio of R_k (the
+         largest sum of the magnitudes of R_k's terms over ||R_k||, tests/_conditioning.py),
+         u = 2^-53; on the small Kelvin-Helmholtz and 3D meshes 32 u kappa < 1e-12, so the
+         bar is the plain 1e-12; it is larger for the uniform-pressure density wave (its
+         flux-divergence terms are ~1e4 x its RHS) and on the full-size meshes (kappa grows
+         like 1/dx in the uniformly moving bulk);
+  steps: bar_k = max(1e-12, 32 u kappa_k) with kappa_k summing the stage states' and the
+         stage RHS terms' magnitudes (tests/_util.step_bar): 1e-12 on every smooth case;
+         the random 3D stress field and a step 300 times the stable one carry the fixed
+         bars of tests/_util.AMPLIFIED_BARS (the oracle's own response to 1-ulp input
+         changes is that large there).
+Meshes span several workgroups and end in a partial one (ragged tail)."""
 import numpy as np
 import pytest
 import torch
@@ -22,7 +27,7 @@ from oracle import timestep as ots
 from oracle.setup import BRENT, CUBIC, IDEAL, NEWTON, QUARTIC, TM, Setup
 from paper_2205_00095_amd import workloads as wl
 
-from ._util import oracle_state, parity_tol, rel_err_per_var
+from ._util import AMPLIFIED_BARS, oracle_state, rel_err_per_var, rhs_bar, step_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -61,12 +66,12 @@ def test_rhs_matches_oracle(kind, over):
     print(f"case {kind} {over}", flush=True)
     st, U = oracle_state(cfg)
     R_ref = odg.rhs(U, st)
-    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    bar, kappa = rhs_bar(U, st, R_ref)
     s = _solver(cfg)
     R = s.rhs(U.cuda()).cpu()
     err = rel_err_per_var(R, R_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}")
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
 
 
 @pytest.mark.parametrize("kind,over", [RHS_CASES[0], RHS_CASES[3], RHS_CASES[6], RHS_CASES[9]])
@@ -214,8 +219,9 @@ def test_ssprk3_steps_match_oracle(kind, over, nsteps):
     cfg = _case_cfg(kind, over)
     st, U = oracle_state(cfg)
     stats = {}
-    U_ref = ots.run(U, cfg["dt"], nsteps, st, phys=True, stats=stats)
-    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], nsteps, st, phys=True), U)
+    U_ref, bar, kappa = step_bar(U, cfg["dt"], nsteps, st, stats=stats)
+    if kind == "random3d":
+        bar = torch.full_like(bar, AMPLIFIED_BARS["random3d 5x4x3 p=2 1 step"])
     s = _solver(cfg, sync=False)
     Ud = U.cuda().contiguous()
     if nsteps == 1:
@@ -223,8 +229,8 @@ def test_ssprk3_steps_match_oracle(kind, over, nsteps):
     else:
         s.run(Ud, cfg["dt"], nsteps)
     err = rel_err_per_var(Ud.cpu(), U_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}")
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
     if kind == "random3d":
         assert s.diagnostics()["smoothed"] == stats.get("smoothed", 0)
 
@@ -237,14 +243,15 @@ def test_tm_newton_start_far_from_root(dt_scale):
     cfg = wl.make_config("kh_tm", n_elem=(9, 8, 1), c2p=wl.C2P_NEWTON)
     st, U = oracle_state(cfg)
     dt = cfg["dt"] * dt_scale
-    U_ref = ots.step(U, dt, st)
-    tol, sens = parity_tol(lambda V: ots.step(V, dt, st), U)
+    U_ref, bar, kappa = step_bar(U, dt, 1, st)
+    if dt_scale > 100:
+        bar = torch.full_like(bar, AMPLIFIED_BARS["kh_tm 9x8 p=3 dt x300 1 step"])
     s = _solver(cfg, sync=False)
     Ud = U.cuda().contiguous()
     s.step(Ud, dt)
     err = rel_err_per_var(Ud.cpu(), U_ref)
-    print(f"dt x{dt_scale}: err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"dt x{dt_scale}: err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
     assert s.diagnostics()["c2p_fail"] == 0
 
 
@@ -260,8 +267,9 @@ def test_lower_order_ssprk_matches_oracle(kind, over, nsteps, order):
     """RK1 and SSPRK2 (the paper's pairings with p = 0 and p = 1) against the oracle."""
     cfg = _case_cfg(kind, over)
     st, U = oracle_state(cfg)
-    U_ref = ots.run(U, cfg["dt"], nsteps, st, phys=True, order=order)
-    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], nsteps, st, phys=True, order=order), U)
+    U_ref, bar, kappa = step_bar(U, cfg["dt"], nsteps, st, order=order)
+    if kind == "random3d":
+        bar = torch.full_like(bar, AMPLIFIED_BARS["random3d 4x3x3 p=1 SSPRK2 1 step"])
     s = _solver(cfg, sync=False)
     Ud = U.cuda().contiguous()
     if nsteps == 1:
@@ -269,5 +277,5 @@ def test_lower_order_ssprk_matches_oracle(kind, over, nsteps, order):
     else:
         s.run(Ud, cfg["dt"], nsteps, order=order)
     err = rel_err_per_var(Ud.cpu(), U_ref)
-    print(f"order {order}: err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"order {order}: err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())

@@ -1,7 +1,9 @@
 """The paper's 2D Riemann problems (Sec. 4, 2D Riemann problems, tests 1-3: four
 quadrant states, Gamma = 5/3, outflow boundaries, t = 0.8;
 tests/golden/riemann_problems_2d.txt) on the GPU: parity with the oracle over the first
-steps, and full runs at p = 0 and p = 1 (physicality operator on, no limiter) staying
+steps, each step started from the oracle's own state (the flow is chaotic at the jumps:
+two runs that differ by rounding drift apart by ~1e-5 in six steps, so a whole-run
+comparison cannot separate a kernel error from that drift), and full runs at p = 0 and p = 1 (physicality operator on, no limiter) staying
 admissible, and for tests 1 and 3, whose initial data are symmetric about the diagonal
 (quadrants 2 and 4 mirror images), staying symmetric."""
 import os
@@ -13,7 +15,7 @@ import torch
 from oracle import timestep as ots
 from paper_2205_00095_amd import workloads as wl
 
-from ._util import oracle_state, parity_tol, rel_err_per_var
+from ._util import AMPLIFIED_BARS, rel_err_per_var, step_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -45,21 +47,36 @@ def _setup(N, p, test=1):
 
 
 def test_first_steps_match_oracle():
+    """Six SSPRK2 steps of test 1 at 16x16 p=1, each from the oracle's state, with the same
+    numbers of flagged and smoothed elements and of trace fallbacks as the oracle's step.
+    The operator smooths up to 30 elements per step here and amplifies rounding: a 1-ulp
+    change of the input moves the oracle's step by up to 2.6e-12, above the
+    cancellation-based bar (1e-12), so the fixed bar of tests/_util.AMPLIFIED_BARS holds."""
     from oracle import srhd
     from oracle.setup import Setup
+    from paper_2205_00095_amd.solver import Solver
     cfg, prims, _ = _setup(16, 1)
-    print("case 2D Riemann test 1, 16x16 p=1, 6 steps", flush=True)
     st = Setup.from_config(cfg)
     P = torch.from_numpy(prims)
     U = srhd.prim3_to_cons(P[0], P[1:3], P[3], st).contiguous()
-    U_ref = ots.run(U, cfg["dt"], 6, st, phys=True, order=2)
-    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], 6, st, phys=True, order=2), U)
-    from paper_2205_00095_amd.solver import Solver
-    Ud = U.cuda()
-    Solver(cfg).run(Ud, cfg["dt"], 6, order=2)
-    err = rel_err_per_var(Ud.cpu(), U_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    s = Solver(cfg, sync=False)
+    for k in range(6):
+        print(f"case 2D Riemann test 1, 16x16 p=1, step {k} from the oracle's state", flush=True)
+        stats = {}
+        U_next = ots.step(U, cfg["dt"], st, phys=True, stats=stats, order=2)
+        _, bar, kappa = step_bar(U, cfg["dt"], 1, st, order=2)
+        bar = torch.clamp(bar, min=AMPLIFIED_BARS["riemann2d test 1 16x16 p=1 step"])
+        Ud = U.cuda().contiguous()
+        s.reset_diagnostics()
+        s.step(Ud, cfg["dt"], order=2)
+        d = s.diagnostics()
+        err = rel_err_per_var(Ud.cpu(), U_next)
+        print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()} gpu {d} oracle {stats}", flush=True)
+        assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
+        assert d["flagged"] == stats.get("flagged", 0) and d["smoothed"] == stats.get("smoothed", 0)
+        assert d["trace_fallback"] == stats.get("trace_fallbacks", 0)
+        assert d["bad_average"] == stats.get("bad_average", 0) == 0
+        U = U_next
 
 
 @pytest.mark.parametrize("test", [1, 2, 3])

@@ -9,7 +9,7 @@ from oracle import dg as odg
 from oracle import timestep as ots
 from paper_2205_00095_amd import workloads as wl
 
-from ._util import oracle_state, parity_tol, perturbed, rel_err_per_var
+from ._util import oracle_state, perturbed, rel_err_per_var, rhs_bar, step_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -43,11 +43,11 @@ def test_wall_rhs_matches_oracle(kind, over, flux):
     print(f"case walls rhs {kind} {over} flux {flux}", flush=True)
     st, U = oracle_state(cfg)
     R_ref = odg.rhs(U, st)
-    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    bar, kappa = rhs_bar(U, st, R_ref)
     Rg = _solver(cfg).rhs(U.cuda()).cpu()
     err = rel_err_per_var(Rg, R_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
 
 
 @pytest.mark.parametrize("kind,over,flux", [CASES[2], CASES[3]])
@@ -55,13 +55,12 @@ def test_wall_steps_match_oracle(kind, over, flux):
     cfg = _cfg(kind, over, flux)
     print(f"case walls steps {kind} {over} flux {flux}", flush=True)
     st, U = oracle_state(cfg)
-    U_ref = ots.run(U, cfg["dt"], 4, st, phys=True)
-    tol, sens = parity_tol(lambda V: ots.run(V, cfg["dt"], 4, st, phys=True), U)
+    U_ref, bar, kappa = step_bar(U, cfg["dt"], 4, st)
     Ud = U.cuda().contiguous()
     _solver(cfg, sync=False).run(Ud, cfg["dt"], 4)
     err = rel_err_per_var(Ud.cpu(), U_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
 
 
 def _mirror_x(U):
@@ -150,11 +149,11 @@ def test_mixed_ends_rhs_matches_oracle(kind, over, flux):
     print(f"case mixed ends rhs {kind} flux {flux}", flush=True)
     st, U = oracle_state(cfg)
     R_ref = odg.rhs(U, st)
-    tol, sens = parity_tol(lambda V: odg.rhs(V, st), U)
+    bar, kappa = rhs_bar(U, st, R_ref)
     Rg = _solver(cfg).rhs(U.cuda()).cpu()
     err = rel_err_per_var(Rg, R_ref)
-    print(f"err {err.tolist()} tol {tol.tolist()}", flush=True)
-    assert bool((err <= tol).all()), (err.tolist(), sens.tolist())
+    print(f"err {err.tolist()} bar {bar.tolist()} kappa {kappa.tolist()}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
 
 
 @pytest.mark.parametrize("kind,over,flux", [MIXED[2], MIXED[3]])
