@@ -97,7 +97,8 @@ def _time_con2prim(solver, U, reps=20):
 
 
 def _time_rhs(solver, U, reps=20):
-    """dg_rhs alone: recovery launch + element kernel in RHS mode."""
+    """dg_rhs alone (one fused launch in 1D and 2D: the element kernel recovers its nodes
+    and its halo itself; in 3D with p >= 1 a recovery launch and the element kernel)."""
     import torch
     R = solver.empty()
     solver.rhs(U, out=R)
@@ -575,6 +576,8 @@ def main(argv=None):
                     help="only run the 3D stress-field leg (64^3 p=2) and print its JSON")
     ap.add_argument("--adjoint", action="store_true",
                     help="only run the adjoint cost measurement (128x128 p=2, 200 steps) and print its JSON")
+    ap.add_argument("--rhs", action="store_true",
+                    help="only time dg_rhs on the workload (50 calls after one warm-up) and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -601,6 +604,13 @@ def main(argv=None):
         return 0
     if args.adjoint:
         print(json.dumps(adjoint_ratio()), flush=True)
+        return 0
+    if args.rhs:
+        cfg, solver, U = _setup(args.workload)
+        nvar, dofs = cfg["dim"] + 2, wl.n_dof(cfg)
+        t_rhs = _time_rhs(solver, U, reps=50)
+        print(json.dumps({"workload": args.workload, "dof": dofs, "dg_rhs_us": t_rhs * 1e6,
+                          "frac": 2 * nvar * 8.0 * dofs / t_rhs / 1e9 / HBM_PEAK_GBS}), flush=True)
         return 0
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -654,7 +664,8 @@ def main(argv=None):
             "us": t_rhs * 1e6, "algorithmic_bytes": 2 * nvar * 8.0 * dofs,
             "achieved_GBs": 2 * nvar * 8.0 * dofs / t_rhs / 1e9,
             "frac": 2 * nvar * 8.0 * dofs / t_rhs / 1e9 / HBM_PEAK_GBS,
-            "note": "recovery launch + element kernel in RHS mode; read U, write R"},
+            "note": ("one launch: the element kernel recovers its nodes and halo elements and writes R; "
+                     "algorithmic bytes: read U, write R")},
     }
     if prof:
         # executed-instruction view of the same kernel from the counter summary

@@ -73,7 +73,8 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * step), BRENT (bracketed iteration) or NEWTON (the default: inside an SSP-RK
  * stage, three Newton steps on the same cubic started from the node's primitives
  * of the previous stage and accepted only when converged on the physical root,
- * else the CUBIC result; outside a stage the CUBIC result).  precision = DG_FP32_CONTRACT
+ * else the CUBIC result; outside a stage the same three steps started from the
+ * closed-form root evaluated in FP32, accepted likewise).  precision = DG_FP32_CONTRACT
  * evaluates the volume (D-hat) and lift contractions in FP32 with FP32
  * accumulation, on deviations from an FP64 reference per line of nodes; the face
  * traces, the recovery, the fluxes, the numerical flux, the operator and the RK
@@ -219,9 +220,10 @@ void dg_destroy(dg_ctx* ctx);
  * are as in dg_rhs (caller-owned, [n_var][elements][nodes], not overlapping) and
  * the result equals dg_rhs's bit for bit.  Scratch: a static device array of 64 MiB
  * per GPU, held from the first call on that GPU until the process ends, holding the
- * counters and the primitive staging; meshes whose state holds more than
- * DG_RHS_NOALLOC_MAX_STATE doubles (n_var x elements x (p+1)^dim) are rejected with
- * DG_EINVAL.  The work is enqueued on hip_stream, which must belong to the current
+ * counters and, where dg_rhs stages the primitives between two launches (3D with
+ * p >= 1; elsewhere one launch recovers them in the tile), that staging: there,
+ * meshes whose state holds more than DG_RHS_NOALLOC_MAX_STATE doubles
+ * (n_var x elements x (p+1)^dim) are rejected with DG_EINVAL.  The work is enqueued on hip_stream, which must belong to the current
  * device; the first call on each device resolves the array's address (make it
  * outside a capture).  Every call on one GPU shares that array: calls that overlap
  * on one GPU (several streams or host threads) race.  The counters restart at zero

@@ -42,6 +42,7 @@ int finish(dg_ctx* c, const char* what);
 ElemArgs base_args(dg_ctx* c);
 const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s);
 hipError_t launch_element(const MeshSetup& s, int mode, const ElemArgs& a, hipStream_t st);
+bool fused_rhs(const MeshSetup& s);
 hipError_t launch_con2prim(const MeshSetup& s, const double* U, double* W, Counters* cnt, hipStream_t st);
 hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a);
 hipError_t L_con2prim(dg_ctx* c, const double* U, double* W);

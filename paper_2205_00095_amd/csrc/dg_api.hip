@@ -246,6 +246,23 @@ hipError_t launch_element(const MeshSetup& s, int mode, const ElemArgs& a, hipSt
   return launch_element_dim3(p, eos, prec, mode, fl, a, st);
 }
 
+// Whether the element kernel of this (dim, p) has the fused right-hand side (its halo
+// adds at most one recovery per lane; see TileGeo::kFusedRhs).
+template <int DIM>
+static bool fused_rhs_dim(int p) {
+  switch (p) {
+    case 0: return TileGeo<DIM, 0>::kFusedRhs;
+    case 1: return TileGeo<DIM, 1>::kFusedRhs;
+    case 2: return TileGeo<DIM, 2>::kFusedRhs;
+    default: return TileGeo<DIM, 3>::kFusedRhs;
+  }
+}
+
+bool fused_rhs(const MeshSetup& s) {
+  const int dim = s.desc.dim, p = s.desc.p;
+  return dim == 1 ? fused_rhs_dim<1>(p) : (dim == 2 ? fused_rhs_dim<2>(p) : fused_rhs_dim<3>(p));
+}
+
 hipError_t launch_con2prim(const MeshSetup& s, const double* U, double* W, Counters* cnt, hipStream_t st) {
   const int dim = s.desc.dim, eos = s.desc.eos;
   if (dim == 1) return launch_con2prim_dim1(eos, U, W, s.ntot, s.npe, s.q, cnt, st);
@@ -397,12 +414,19 @@ int dg_rhs(dg_ctx* c, const double* U, double* R) {
   if (!c) return DG_EINVAL;
   if (!U || !R) return fail(c, DG_EINVAL, "dg_rhs: null pointer");
   if (U == R) return fail(c, DG_EINVAL, "dg_rhs: U and R alias");
-  int r = hipcheck(c, L_con2prim(c, U, c->Wa), "dg_rhs/con2prim");
-  if (r) return r;
   ElemArgs a = base_args(c);
-  a.W = c->Wa;
   a.out = R;
-  r = hipcheck(c, L_element(c, MODE_RHS, a), "dg_rhs/element");
+  int r;
+  if (fused_rhs(*c)) {
+    // one launch: every tile recovers its nodes and its halo elements itself
+    a.Uk = U;
+    r = hipcheck(c, L_element(c, MODE_RHS_FUSED, a), "dg_rhs/element");
+  } else {
+    r = hipcheck(c, L_con2prim(c, U, c->Wa), "dg_rhs/con2prim");
+    if (r) return r;
+    a.W = c->Wa;
+    r = hipcheck(c, L_element(c, MODE_RHS, a), "dg_rhs/element");
+  }
   if (r) return r;
   return finish(c, "dg_rhs");
 }
@@ -577,8 +601,11 @@ extern "C" int dg_rhs_noalloc(const dg_mesh_desc* desc, void* hip_stream, const 
   if (why) return noalloc_fail(DG_EINVAL, "%s", why);
   if (!U || !R) return noalloc_fail(DG_EINVAL, "null pointer");
   if (U == R) return noalloc_fail(DG_EINVAL, "U and R alias");
+  // the same kernels as dg_rhs: one fused launch, or (3D, p >= 1) a recovery launch
+  // staging the primitives in the scratch and the element kernel reading them
+  const bool fused = fused_rhs(s);
   const size_t need = (size_t)s.nv * (size_t)s.ntot;
-  if (need > (size_t)DG_RHS_NOALLOC_MAX_STATE)
+  if (!fused && need > (size_t)DG_RHS_NOALLOC_MAX_STATE)
     return noalloc_fail(DG_EINVAL, "the mesh needs %zu doubles of primitive staging; the static scratch holds %zu",
                         need, (size_t)DG_RHS_NOALLOC_MAX_STATE);
   unsigned char* base = nullptr;
@@ -590,7 +617,7 @@ extern "C" int dg_rhs_noalloc(const dg_mesh_desc* desc, void* hip_stream, const 
   // the counters start at zero on every call (a kernel, not a memset node)
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt);
   e = hipGetLastError();
-  if (e == hipSuccess) e = launch_con2prim(s, U, W, cnt, st);
+  if (e == hipSuccess && !fused) e = launch_con2prim(s, U, W, cnt, st);
   if (e == hipSuccess) {
     ElemArgs a{};
     a.m = s.m;
@@ -598,9 +625,14 @@ extern "C" int dg_rhs_noalloc(const dg_mesh_desc* desc, void* hip_stream, const 
     a.q = s.q;
     a.cnt = cnt;
     a.phys = s.desc.phys;
-    a.W = W;
     a.out = R;
-    e = launch_element(s, MODE_RHS, a, st);
+    if (fused) {
+      a.Uk = U;
+      e = launch_element(s, MODE_RHS_FUSED, a, st);
+    } else {
+      a.W = W;
+      e = launch_element(s, MODE_RHS, a, st);
+    }
   }
   if (e != hipSuccess) return noalloc_fail(DG_EHIP, "launch: %s", hipGetErrorString(e));
   if (!diag && !s.desc.sync_mode) return DG_OK;

@@ -356,7 +356,11 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
 }
 
 // ------------------------------------------------------------ element kernel
-enum { MODE_RHS = 0, MODE_STAGE = 1 };
+// MODE_RHS reads the primitives of the nodes from HBM (a recovery launch wrote them);
+// MODE_RHS_FUSED reads U and recovers its own nodes and the halo elements across the
+// tile's boundary faces itself (one launch, no primitive buffer); MODE_STAGE is one
+// SSP-RK stage.
+enum { MODE_RHS = 0, MODE_STAGE = 1, MODE_RHS_FUSED = 2 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1 };
 
 // Tile of elements handled by one workgroup of k_element: TX x TY x TZ elements,
@@ -382,6 +386,12 @@ struct TileGeo {
   static constexpr int FOFF2 = FOFF1 + NFY * NFP;
   static constexpr int FPB = FOFF2 + NFZ * NFP;  // face points per tile
   static_assert(NT <= 256, "tile larger than a workgroup");
+  // halo of the fused right-hand side: the elements across the tile's lowest and highest
+  // active faces along each direction, C_d of them per side (the tile's cross-section)
+  static constexpr int C0 = TY * TZ, C1 = DIM > 1 ? TX * TZ : 0, C2 = DIM > 2 ? TX * TY : 0;
+  static constexpr int NHE = 2 * (C0 + C1 + C2);
+  // the fused right-hand side is built where the halo adds at most one recovery per lane
+  static constexpr bool kFusedRhs = NHE * NPE <= NT;
 };
 
 // index of the face point (direction d, face coordinate f along d, the other two local
@@ -539,6 +549,59 @@ __device__ __forceinline__ int xcd_tile(int b, int nb, int rev = 0) {
   return x * q + min(x, r) + (rev ? cnt - 1 - k : k);
 }
 
+// Halo element hs of a tile (TileGeo::NHE of them): direction d, side (0: across the
+// lowest active face along d, 1: across the highest), position c in the tile's
+// cross-section.  Returns its global element after the periodic wrap, or -1 where
+// there is none (a non-periodic mesh end, or a cross-section position outside the mesh).
+template <int DIM, int P>
+__device__ __forceinline__ long long halo_element(int hs, const int* o, const MeshArgs& m) {
+  using T = TileGeo<DIM, P>;
+  int d, r;
+  if (hs < 2 * T::C0) { d = 0; r = hs; }
+  else if (DIM == 2 || hs < 2 * (T::C0 + T::C1)) { d = 1; r = hs - 2 * T::C0; }
+  else { d = 2; r = hs - 2 * (T::C0 + T::C1); }
+  const int cd = sel3(d, T::C0, T::C1, T::C2);
+  const int side = r >= cd ? 1 : 0;
+  const int c = r - side * cd;
+  int l[3];
+  if (d == 0) { l[0] = 0; l[1] = c % T::TY; l[2] = c / T::TY; }
+  else if (d == 1) { l[0] = c % T::TX; l[1] = 0; l[2] = c / T::TX; }
+  else { l[0] = c % T::TX; l[1] = c / T::TX; l[2] = 0; }
+  const int n[3] = {m.nex, m.ney, m.nez};
+  int g[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[k] = o[k] + l[k];
+  // the cross-section position must lie in the mesh
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k != d && g[k] >= n[k]) return -1;
+  const int td = sel3(d, T::TX, T::TY, T::TZ);
+  const int od = sel3(d, o[0], o[1], o[2]);
+  const int nd = sel3(d, n[0], n[1], n[2]);
+  const int nact = min(td, nd - od);  // active elements of the tile along d
+  int gd = side ? od + nact : od - 1;
+  if (gd < 0 || gd >= nd) {
+    if (!sel3(d, m.periodic[0], m.periodic[1], m.periodic[2])) return -1;
+    gd = gd < 0 ? gd + nd : gd - nd;
+  }
+  if (d == 0) g[0] = gd; else if (d == 1) g[1] = gd; else g[2] = gd;
+  return ((long long)g[2] * m.ney + g[1]) * m.nex + g[0];
+}
+
+// Halo slot of the element across face point fc when that element is not in the tile:
+// side 1 for a face whose left element is in the tile (the highest active face), else 0.
+template <int DIM, int P>
+__device__ __forceinline__ int halo_slot(int d, bool a_left, int loc0) {
+  using T = TileGeo<DIM, P>;
+  int c;
+  if (d == 0) c = loc0 / T::TX;
+  else if (d == 1) c = (loc0 / (T::TX * T::TY)) * T::TX + loc0 % T::TX;
+  else c = loc0;
+  const int off = d == 0 ? 0 : (d == 1 ? 2 * T::C0 : 2 * (T::C0 + T::C1));
+  const int cd = sel3(d, T::C0, T::C1, T::C2);
+  return off + (a_left ? cd : 0) + c;
+}
+
 enum { BC_OUTFLOW = 1, BC_REFLECT = 2, BC_FIXED = 3 };
 
 // Exterior state at a boundary face of direction d from the interior trace Wi: outflow
@@ -632,6 +695,11 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   __shared__ double sFref[(PREC == PREC_FP32) ? DIM * NV * EPB * NFP : 1];
   __shared__ int sflag[(MODE == MODE_STAGE) ? NT : 1];
   __shared__ int svote[(NT + 63) / 64];
+  // fused right-hand side: the primitives of the halo elements, recovered in the tile
+  constexpr bool kFused = MODE == MODE_RHS_FUSED;
+  static_assert(!kFused || T::kFusedRhs, "fused right-hand side needs a halo of at most one node per lane");
+  constexpr int NHP = T::NHE * ES;
+  __shared__ double sWh[kFused ? NV * NHP : 1];
 
   const MeshArgs& m = a.m;
   const Tables& t = a.t;
@@ -649,8 +717,34 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   const long long g = e * NPE + node;
 
   double W[NV];
+  if constexpr (kFused) {
+    // recover this node's primitives and those of one halo node (at most), both loads first
+    constexpr int NHN = T::NHE * NPE;
+    const int hs = tid / NPE;  // halo element of this lane's halo node (tid < NHN)
+    const long long hg = tid < NHN ? halo_element<DIM, P>(hs, o, m) : -1;
+    double u[NV], uh[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) W[v] = act ? a.W[v * ntot + g] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
+    for (int v = 0; v < NV; ++v) u[v] = act ? a.Uk[v * ntot + g] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uh[v] = hg >= 0 ? a.Uk[v * ntot + hg * NPE + node] : 0.0;
+    if (act) {
+      const int st = con2prim<EOS, DIM>(u, W, q);
+      count_c2p(counter_slot(a.cnt), st, e);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) W[v] = (v == 0 || v == NV - 1) ? 1.0 : 0.0;
+    }
+    if (hg >= 0) {
+      // counted by the tile that owns the element, not here
+      double wh[NV];
+      (void)con2prim<EOS, DIM>(uh, wh, q);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sWh[v * NHP + hs * ES + node] = wh[v];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) W[v] = act ? a.W[v * ntot + g] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
+  }
   const int ln = el * ES + node;  // this node's slot in sW and sF
 #pragma unroll
   for (int v = 0; v < NV; ++v) sW[v * NTP + ln] = W[v];
@@ -708,7 +802,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   // rhs mode: the volume result waits in sF (free from here on) through the face phase,
   // which lowers the register peak to 6 waves per SIMD for 2D p = 3 (measured 3% faster;
   // the stage kernel gains nothing from it)
-  constexpr bool kParkR = MODE == MODE_RHS && PREC == PREC_FP64;
+  constexpr bool kParkR = (MODE == MODE_RHS || MODE == MODE_RHS_FUSED) && PREC == PREC_FP64;
   if constexpr (kParkR) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) sF[v * NTP + ln] = R[v];
@@ -738,7 +832,12 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     } else {
       const long long ge = a_left ? fc.right_global() : fc.left_global();
       if (ge >= 0) {
-        nfb += trace_glb<NV, P>(a.W + ge * NPE + (a_left ? bwd0 : fwd0), ntot, a_left ? -stride : stride, t, WB);
+        if constexpr (kFused) {
+          const int hb = halo_slot<DIM, P>(d, a_left, fc.loc0) * ES;
+          nfb += trace_lds<NV, NHP, P>(sWh, hb + (a_left ? bwd0 : fwd0), a_left ? -stride : stride, t, WB);
+        } else {
+          nfb += trace_glb<NV, P>(a.W + ge * NPE + (a_left ? bwd0 : fwd0), ntot, a_left ? -stride : stride, t, WB);
+        }
       } else {
         // no neighbour: a boundary face (side A's element is below it at the upper end)
         exterior_state<DIM>(m, d, a_left, WA, WB);
@@ -822,7 +921,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   }
 
   // ---- epilogue
-  if constexpr (MODE == MODE_RHS) {
+  if constexpr (MODE == MODE_RHS || MODE == MODE_RHS_FUSED) {
     if (act) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = R[v];

@@ -28,6 +28,10 @@ hipError_t by_flux(int flux, const ElemArgs& a, hipStream_t s) {
 
 template <int DIM, int P, int EOS, int PREC>
 hipError_t by_mode(int mode, int flux, const ElemArgs& a, hipStream_t s) {
+  if (mode == MODE_RHS_FUSED) {
+    if constexpr (TileGeo<DIM, P>::kFusedRhs) return by_flux<DIM, P, EOS, PREC, MODE_RHS_FUSED>(flux, a, s);
+    return hipErrorInvalidValue;
+  }
   return mode == MODE_RHS ? by_flux<DIM, P, EOS, PREC, MODE_RHS>(flux, a, s)
                           : by_flux<DIM, P, EOS, PREC, MODE_STAGE>(flux, a, s);
 }

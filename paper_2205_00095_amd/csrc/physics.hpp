@@ -369,6 +369,44 @@ __host__ __device__ __forceinline__ void tm_cubic_scaled(double X, double Y, dou
   C3 = -9.0 * x2 * e2;
 }
 
+// A start for Newton on the TM cubic A W^3 + C1 W^2 + C2 W + C3 (tm_cubic_scaled): its
+// largest root by the closed form of the monic cubic evaluated in FP32 (relative error
+// ~1e-6 away from a double root; three FP64 Newton steps then reach rounding level, and
+// the caller accepts the result only when the last step is that small).
+__host__ __device__ __forceinline__ double tm_cubic_start_f32(double A, double C1, double C2, double C3) {
+  const float ia = 1.0f / (float)A;
+  const float c1 = (float)C1 * ia, c2 = (float)C2 * ia, c3 = (float)C3 * ia;
+  const float Q = (3.0f * c2 - c1 * c1) * (1.0f / 9.0f);
+  const float R = (9.0f * c1 * c2 - 27.0f * c3 - 2.0f * c1 * c1 * c1) * (1.0f / 54.0f);
+  const float dd = Q * Q * Q + R * R;
+  float W;
+  if (dd < 0.0f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float irq = rsqrtf(-Q * Q * Q);
+#else
+    const float irq = 1.0f / sqrtf(-Q * Q * Q);
+#endif
+    const float x = fminf(1.0f, fmaxf(-1.0f, R * irq));
+    float t;
+    if (x > -0.9f) {
+      // cos(acos(x) / 3): the fit of cos_third_acos and two Newton steps on 4 t^3 - 3 t = x
+      t = (((-0.0366375f * x + 0.0517291f) * x - 0.0412189f) * x + 0.159253f) * x + 0.865755f;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const float t2 = t * t;
+        t -= (t * (4.0f * t2 - 3.0f) - x) / (12.0f * t2 - 3.0f);
+      }
+    } else {
+      t = cosf(acosf(x) * (1.0f / 3.0f));
+    }
+    W = 2.0f * sqrtf(-Q) * t - c1 * (1.0f / 3.0f);
+  } else {
+    const float sd = sqrtf(dd);
+    W = -c1 * (1.0f / 3.0f) + cbrtf(R + sd) + cbrtf(R - sd);
+  }
+  return (double)W;
+}
+
 // Brent's bracketed root finder (inverse quadratic interpolation / secant with
 // bisection safeguard) on the TM cubic over [lo, hi]; returns false at the cap.
 __host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, double c3, double lo, double hi, double& root) {
@@ -423,10 +461,11 @@ __host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, dou
 // status; on failure writes the floor state.  Also returns the pieces the
 // implicit-function-theorem adjoint needs through the primitive output only.
 // Wprev, when given, is the node's primitive state of the previous SSP-RK stage: with
-// the TM EOS and C2P_NEWTON it starts three Newton steps on the cubic, accepted when
-// the last step is below 1e-9 W and the iterate lies on the branch of the largest
-// root (f' > 0 beyond the inflection point); otherwise, and without Wprev, the
-// analytic root with one Newton polish.  Both give the same root to rounding.  With
+// the TM EOS and C2P_NEWTON it starts three Newton steps on the cubic (without Wprev the
+// closed-form root evaluated in FP32 starts them), accepted when the last step is below
+// 1e-9 W and the iterate lies on the branch of the largest root (f' > 0 beyond the
+// inflection point); otherwise the analytic root with one Newton polish.  Both give
+// the same root to rounding.  With
 // the ideal EOS and C2P_NEWTON it is the start of the Newton iteration on the quartic
 // (any start in (0, 1) converges to its one root there; the stop rule is unchanged).
 // known_admissible: the caller has evaluated admissible<DIM>(U) (the same expression)
@@ -539,18 +578,24 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
     } else {
       double Wc;
       bool done = false;
-      if (method == C2P_NEWTON && Wprev != nullptr) {
+      if (method == C2P_NEWTON) {
         // Newton on the cubic scaled by 16 D^4 (eta^2 - xi^2)^2 (the same iterates as on
         // the monic one, without a division for the coefficients), its coefficients from
-        // (X, Y, D) / 2^e with 2^e the binade of D
+        // (X, Y, D) / 2^e with 2^e the binade of D; started from the previous stage's
+        // root inside a stage, else from the closed-form root in FP32
         int e;
         (void)frexp(D, &e);
         double A, C1, C2, C3;
         tm_cubic_scaled(ldexp(Smag * q.inv_c, -e), ldexp(tau * q.inv_c2 + D, -e), ldexp(D, -e), A, C1, C2, C3);
-        double u2 = 0.0;
+        double Wn;
+        if (Wprev != nullptr) {
+          double u2 = 0.0;
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) u2 += Wprev[1 + j] * Wprev[1 + j];
-        double Wn = u2 * q.inv_c2;  // gamma^2 - 1 of the previous stage
+          for (int j = 0; j < DIM; ++j) u2 += Wprev[1 + j] * Wprev[1 + j];
+          Wn = u2 * q.inv_c2;  // gamma^2 - 1 of the previous stage
+        } else {
+          Wn = tm_cubic_start_f32(A, C1, C2, C3);
+        }
         double step = 0.0;
 #pragma unroll
         for (int it = 0; it < 3; ++it) {

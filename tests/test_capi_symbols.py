@@ -95,9 +95,12 @@ def test_noalloc_rejections_happen_on_the_host():
     assert lib.dg_rhs_noalloc(ctypes.byref(d), None, fake_u, fake_u, None) == _lib.DG_EINVAL
     bad = _desc(p=5)
     assert lib.dg_rhs_noalloc(ctypes.byref(bad), None, fake_u, fake_r, None) == _lib.DG_EINVAL
-    # 1D p=2: 3 variables x 3 nodes per element; one element more than the scratch holds
-    n_fit = _lib.RHS_NOALLOC_MAX_STATE // 9
-    big = _desc(n_elem=(n_fit + 1, 1, 1))
+    # 3D p=2 (the shapes whose primitives are staged in the scratch): 5 variables x 27
+    # nodes per element; one element more than the scratch holds
+    from paper_2205_00095_amd import workloads as wl
+    from paper_2205_00095_amd.solver import _desc_from_config
+    n_fit = _lib.RHS_NOALLOC_MAX_STATE // 135
+    big = _desc_from_config(wl.make_config("random3d", n_elem=(n_fit + 1, 1, 1)), False)
     assert lib.dg_rhs_noalloc(ctypes.byref(big), None, fake_u, fake_r, None) == _lib.DG_EINVAL
 
 
