@@ -263,7 +263,120 @@ def con2prim_study(runs=100):
         del srcb, Ub, Wb
     return {"study": "25x25 (gamma in [1,100], P in [1e5,1e10] Pa), 10^3 cells x 27 points, "
                      f"{runs} runs per state, c = 3e8 m/s, D = 1; also all 625 states tiled over 7.08M points",
-            "solvers": out}
+            "solvers": out, "fixed_iterations": con2prim_fixed_study(runs)}
+
+
+# velocity errors at or below this count as equal in the iterations-to-parity study
+PARITY_FLOOR = 1e-15
+
+
+def grid_velocity_errors(eos, method, iters=0, c=3.0e8):
+    """Relative velocity error of one GPU recovery solver (dg_con2prim, `iters` > 0 fixing
+    its iteration count) on the paper's 25x25 (gamma, P) grid, as a [P, gamma] array."""
+    import numpy as np
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    from paper_2205_00095_amd.solver import Solver
+    G, PP = wl.c2p_grid(25, c=c)
+    g, P = G.ravel(), PP.ravel()
+    beta = np.sqrt((1 - 1 / g) * (1 + 1 / g))
+    cfg = wl.make_config("random3d", n_elem=(g.size, 1, 1), p=0, eos=eos, c2p=method, c=c,
+                         precision=wl.FP64, c2p_iters=iters)
+    s = Solver(cfg)
+    src = np.stack([1.0 / g, beta * c, 0 * g, 0 * g, P]).reshape((5,) + wl.field_shape(cfg))
+    U = s.set_state(torch.from_numpy(np.ascontiguousarray(src)).cuda())
+    W = s.con2prim(U).reshape(5, -1).cpu().numpy()
+    s.close()
+    v = W[1] / np.sqrt(1 + (W[1:4] ** 2).sum(0) / c ** 2)
+    err = np.where(beta > 0, np.abs(v - beta * c) / np.where(beta > 0, beta * c, 1.0), np.abs(v))
+    return err.reshape(G.shape)
+
+
+def _per_gamma(err):
+    """Median and quartiles over the pressures at each Lorentz factor (the paper's right panels)."""
+    import numpy as np
+    q = np.percentile(err, [25, 50, 75], axis=0)
+    return {"q25": q[0].tolist(), "median": q[1].tolist(), "q75": q[2].tolist()}
+
+
+def con2prim_fixed_study(runs=100, max_iters=60):
+    """The rest of the paper's recovery study (Sec. 3.3) on the GPU:
+
+    * accuracy: the velocity error of the analytic solvers and of the iterative ones at
+      fixed iteration counts (ideal gas: Newton from w = 1/2, 6 and 12 steps; TM: Brent on
+      [0, 200^2 - 1], 25 and 50 steps) on the 25x25 grid;
+    * iterations to parity: the fewest iterations (1 .. max_iters) with which the
+      iterative solver is at least as accurate as the analytic one, per state (-1 where it
+      never gets there); an error at or below PARITY_FLOOR (a few ulps of the velocity)
+      counts as matching, so that ties at rounding level do not decide it;
+    * timing: analytic time / iterative time (at the parity count) - 1 per state, each
+      state on 10^3 cells x 27 points (the paper's size; one launch there is mostly launch
+      latency) and on 64^3 x 27 = 7.08M points, `runs` and 10 runs."""
+    import numpy as np
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    from paper_2205_00095_amd.solver import Solver
+    c = 3.0e8
+    G, PP = wl.c2p_grid(25, c=c)
+    out = {"gamma": G[0].tolist(), "pressure": PP[:, 0].tolist()}
+    stream = torch.cuda.current_stream()
+    for eos, analytic, iterative, caps, name in ((wl.EOS_IDEAL, wl.C2P_QUARTIC, wl.C2P_NEWTON, (6, 12), "ideal"),
+                                                  (wl.EOS_TM, wl.C2P_CUBIC, wl.C2P_BRENT, (25, 50), "tm")):
+        ea = grid_velocity_errors(eos, analytic)
+        rec = {"analytic": {"max": float(ea.max()), "per_gamma": _per_gamma(ea)}}
+        for n in caps:
+            e = grid_velocity_errors(eos, iterative, n)
+            rec[f"iterative_{n}"] = {"max": float(e.max()), "per_gamma": _per_gamma(e)}
+        parity = np.full(ea.shape, -1, dtype=np.int64)
+        for n in range(1, max_iters + 1):
+            e = grid_velocity_errors(eos, iterative, n)
+            newly = (parity < 0) & (e <= np.maximum(ea, PARITY_FLOOR))
+            parity[newly] = n
+        ok = parity > 0
+        rec["iterations_to_parity"] = {
+            "map": parity.tolist(), "never": int((~ok).sum()),
+            "median_per_gamma": [float(np.median(col[col > 0])) if (col > 0).any() else None for col in parity.T],
+            "max": int(parity[ok].max()) if ok.any() else None}
+        # timing per state at its parity count (states that never reach parity are skipped)
+        ratios = {"27k": np.full(ea.shape, np.nan), "7M": np.full(ea.shape, np.nan)}
+        for size, n_elem, reps in (("27k", (10, 10, 10), runs), ("7M", (64, 64, 64), 10)):
+            solvers = {}
+            for (i, j) in zip(*np.nonzero(ok)):
+                g, P = G[i, j], PP[i, j]
+                times = []
+                for method, iters in ((analytic, 0), (iterative, int(parity[i, j]))):
+                    key = (method, iters)
+                    if key not in solvers:
+                        solvers[key] = Solver(wl.make_config("random3d", n_elem=n_elem, p=2, eos=eos, c2p=method,
+                                                             c=c, precision=wl.FP64, c2p_iters=iters))
+                    s = solvers[key]
+                    src = torch.empty(s.shape, dtype=torch.float64, device="cuda")
+                    beta = np.sqrt((1 - 1 / g) * (1 + 1 / g))
+                    src[0].fill_(1.0 / g)
+                    src[1].fill_(beta * c)
+                    src[2].zero_()
+                    src[3].zero_()
+                    src[4].fill_(P)
+                    U = s.set_state(src)
+                    W = s.con2prim(U)
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        s.con2prim(U, out=W)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                    del src, U, W
+                ratios[size][i, j] = times[0] / times[1] - 1.0
+            for s in solvers.values():
+                s.close()
+        rec["timing_analytic_over_iterative_minus_1"] = {
+            size: {"median": float(np.nanmedian(r)),
+                   "per_gamma_median": [float(np.nanmedian(col)) if np.isfinite(col).any() else None for col in r.T]}
+            for size, r in ratios.items()}
+        out[name] = rec
+    return out
 
 
 def random3d_leg(repeats=5):

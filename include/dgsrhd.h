@@ -84,7 +84,13 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * the faces (Sec. 2.4): DG_FLUX_HLL (0, the default when the field is zeroed) or
  * DG_FLUX_HLLC, the HLLC solver of Mignone & Bodo (2005) with one contact wave
  * inside the HLL fan (exact on isolated contacts, including tangential-velocity
- * jumps); the adjoint entry points differentiate whichever flux is selected. */
+ * jumps); the adjoint entry points differentiate whichever flux is selected.
+ * c2p_iters (0: off) fixes the iteration count of the iterative recovery solvers
+ * for the recovery study of Sec. 3.3: with the ideal EOS exactly c2p_iters Newton
+ * steps started from w = 1/2, the middle of the interval every start converges from
+ * (no convergence test), with the TM EOS and c2p = BRENT at most c2p_iters Brent
+ * steps on the bracket [0, 200^2 - 1]; no failure is counted for stopping there.  Valid
+ * range 0..1000 (DG_EINVAL outside). */
 typedef struct {
   int dim, p;
   int n_elem[3];
@@ -101,6 +107,7 @@ typedef struct {
   int flux;
   int bc_hi[3];
   double bc_state[3][2][5];
+  int c2p_iters;
 } dg_mesh_desc;
 
 typedef struct {

@@ -32,6 +32,14 @@ tm_brent       Sec. 3.2, iterative: Brent's method (scipy.optimize.brentq) on th
                same cubic, bracket W in [0, 200^2 - 1] expanded by 4x until it
                brackets.
 
+Fixed iteration counts (Sec. 3.3, the recovery study: 6 and 12 Newton iterations,
+25 and 50 for the TM iterative solver; Setup.c2p_iters > 0): ideal_newton runs
+exactly that many Newton steps from w = 1/2 with no convergence test; the TM iterative solver runs Brent's method
+as published (brent_steps below, Brent 1973, "zero" with tolerance 2 eps |b|) for at
+most that many steps, because scipy's brentq does not expose its iterate after a
+given number of steps.  brent_steps is pinned against scipy's brentq at
+convergence, by the bracket it keeps at every step and by its step count bound.
+
 Failure convention (reading; the paper does not specify one): if D <= 0 or
 q <= 0 (Eq. physicality) or the recovered P <= 0, the node gets
 rho = 1e-10, u = 0, P = 1e-10 c^2 and a nonzero status.
@@ -84,7 +92,7 @@ def _finish(ok, D, Smag, nhat, gam, gb, rho, P, st, status):
     return torch.cat([rho[None], u, P[None]], 0), status
 
 
-def ideal_newton(U, st, tol=1e-13, max_iter=30, series_below=1e-4):
+def ideal_newton(U, st, tol=1e-13, max_iter=30, series_below=1e-4, w_start=None):
     c, G = st.c, st.gamma_ad
     ok, D, S, tau, Smag, nhat, xi, t = _prep(U, st)
     alpha = G / (G - 1.0)
@@ -95,6 +103,8 @@ def ideal_newton(U, st, tol=1e-13, max_iter=30, series_below=1e-4):
     Dd = 2.0 * (alpha * t + alpha - 1.0)     # 2 (alpha eta - 1)
     b = xi / eta
     w = b / (1.0 + torch.sqrt(1.0 - b * b))
+    if w_start is not None:
+        w = torch.full_like(w, w_start)
     small = xi < series_below
     active = ok & ~small
     for _ in range(max_iter):
@@ -235,11 +245,94 @@ def tm_brent(U, st, xtol=1e-300, rtol=4.0 * np.finfo(float).eps):
     return _tm_recover(ok, D, tau, Smag, nhat, W, st, status)
 
 
+def brent_steps(f, a, b, max_steps, history=None):
+    """Brent's root finder (Brent 1973, the procedure "zero") on [a, b] with f(a) f(b) <= 0:
+    at each step keep b the best iterate and c the other end of a bracket [b, c]; try
+    inverse quadratic interpolation through (a, b, c) (the secant when a = c), accept the
+    step only if it lands well inside the bracket and shrinks faster than the step before
+    the last, else bisect.  Tolerance 2 eps |b|.  Returns b after convergence or after
+    max_steps function evaluations; history, if a list, receives (b, c, f(b), f(c)) at
+    every step."""
+    eps = float(np.finfo(float).eps)
+    fa, fb = f(a), f(b)
+    c, fc = a, fa
+    d = e = b - a
+    for _ in range(max_steps):
+        if (fb > 0) == (fc > 0):
+            # the bracket is [a, b]: restart from the old iterate
+            c, fc = a, fa
+            d = e = b - a
+        if abs(fc) < abs(fb):
+            # b must be the end with the smaller residual
+            a, fa = b, fb
+            b, fb = c, fc
+            c, fc = a, fa
+        tol = 2.0 * eps * abs(b)
+        m = 0.5 * (c - b)
+        if history is not None:
+            history.append((b, c, fb, fc))
+        if abs(m) <= tol or fb == 0.0:
+            return b
+        if abs(e) >= tol and abs(fa) > abs(fb):
+            s = fb / fa
+            if a == c:
+                p, q = 2.0 * m * s, 1.0 - s
+            else:
+                qa, r = fa / fc, fb / fc
+                p = s * (2.0 * m * qa * (qa - r) - (b - a) * (r - 1.0))
+                q = (qa - 1.0) * (r - 1.0) * (s - 1.0)
+            if p > 0:
+                q = -q
+            p = abs(p)
+            if 2.0 * p < min(3.0 * m * q - abs(tol * q), abs(e * q)):
+                e, d = d, p / q
+            else:
+                d = e = m
+        else:
+            d = e = m
+        a, fa = b, fb
+        b += d if abs(d) > tol else (tol if m > 0 else -tol)
+        fb = f(b)
+    return b
+
+
+def tm_brent_fixed(U, st, max_steps):
+    """The TM iterative solver with at most max_steps Brent steps (the recovery study)."""
+    ok, D, S, tau, Smag, nhat, xi, t = _prep(U, st)
+    eta = 1.0 + t
+    c1, c2, c3 = _tm_coeffs(xi, eta)
+    c1n, c2n, c3n = (v.detach().reshape(-1).numpy() for v in (c1, c2, c3))
+    okn = ok.reshape(-1).numpy()
+    Wn = np.zeros_like(c1n)
+    for k in range(Wn.size):
+        if not okn[k] or c3n[k] == 0.0:
+            continue
+        f = (lambda W, a=c1n[k], b=c2n[k], cc=c3n[k]: ((W + a) * W + b) * W + cc)
+        hi = 200.0 ** 2 - 1.0
+        while f(hi) < 0:
+            hi *= 4.0
+        Wn[k] = brent_steps(f, 0.0, hi, max_steps)
+    W = torch.from_numpy(Wn).reshape(xi.shape)
+    status = torch.where(ok, torch.zeros_like(xi, dtype=torch.int32),
+                         torch.full_like(xi, ST_INADMISSIBLE, dtype=torch.int32))
+    return _tm_recover(ok, D, tau, Smag, nhat, W, st, status)
+
+
 def con2prim(U, st, method=None):
     """U [nvar, ...] -> (W [nvar, ...], status int32 [...])."""
     m = st.c2p if method is None else method
     if m < 0:
         m = NEWTON if st.eos == IDEAL else CUBIC
+    fixed = getattr(st, "c2p_iters", 0)
+    if st.eos == IDEAL and m == NEWTON and fixed > 0:
+        # exactly `fixed` Newton steps from w = 1/2 (a negative tolerance never stops the
+        # iteration).  Reading: the paper's study does not give its start; the middle of
+        # (0, 1), from which it says any start converges, reproduces the pattern it
+        # describes (6 steps near machine precision below gamma 10, 12 for all gamma).
+        W, status = ideal_newton(U, st, tol=-1.0, max_iter=fixed, w_start=0.5)
+        return W, torch.where(status == ST_NOCONV, torch.zeros_like(status), status)
+    if st.eos == TM and m == BRENT and fixed > 0:
+        return tm_brent_fixed(U, st, fixed)
     if st.eos == IDEAL and m == NEWTON:
         return ideal_newton(U, st)
     if st.eos == IDEAL and m == QUARTIC:

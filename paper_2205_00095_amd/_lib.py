@@ -31,6 +31,7 @@ class MeshDesc(ctypes.Structure):
         ("flux", ctypes.c_int),
         ("bc_hi", ctypes.c_int * 3),
         ("bc_state", ctypes.c_double * 30),
+        ("c2p_iters", ctypes.c_int),
     ]
 
 

@@ -193,6 +193,7 @@ const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s) {
   if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT) return "unknown precision";
   if (d.flux != DG_FLUX_HLL && d.flux != DG_FLUX_HLLC) return "flux must be HLL or HLLC";
   if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
+  if (d.c2p_iters < 0 || d.c2p_iters > 1000) return "c2p_iters must be in 0..1000";
   const long long nelem = (long long)d.n_elem[0] * d.n_elem[1] * d.n_elem[2];
   if (nelem > (1ll << 30)) return "mesh too large";
   s.nv = d.dim + 2;
@@ -210,6 +211,7 @@ const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s) {
   q.alpha = (d.eos == DG_EOS_IDEAL) ? d.gamma_ad / (d.gamma_ad - 1.0) : 0.0;
   q.eps = d.phys_eps;
   q.c2p = d.c2p;
+  q.c2p_iters = d.c2p_iters;
   gl_tables(d.p, d.dim, s.t);
   MeshArgs& m = s.m;
   m.nex = d.n_elem[0];

@@ -28,6 +28,9 @@ struct PhysParams {
   double alpha;  // Gamma / (Gamma - 1)
   double eps;    // relative margin of the physicality operator
   int c2p;       // recovery solver
+  int c2p_iters; // > 0: the fixed-iteration solvers of the recovery study (Sec. 3.3): exactly
+                 // this many Newton steps from w = 1/2 (ideal EOS, no convergence test) or
+                 // at most this many Brent steps (TM EOS)
 };
 
 // ---------------------------------------------------------------- EOS (Sec. 2.2)
@@ -407,14 +410,16 @@ __host__ __device__ __forceinline__ double tm_cubic_start_f32(double A, double C
   return (double)W;
 }
 
-// Brent's bracketed root finder (inverse quadratic interpolation / secant with
-// bisection safeguard) on the TM cubic over [lo, hi]; returns false at the cap.
-__host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, double c3, double lo, double hi, double& root) {
+// Brent's bracketed root finder (R. P. Brent, Algorithms for Minimization without
+// Derivatives, 1973: inverse quadratic interpolation / secant with a bisection
+// safeguard) on the TM cubic over [lo, hi]; returns false at the cap of maxit steps.
+__host__ __device__ __forceinline__ bool tm_brent_root(double c1, double c2, double c3, double lo, double hi, double& root,
+                                                      int maxit = 100) {
   auto f = [&](double W) { return ((W + c1) * W + c2) * W + c3; };
   double a = lo, b = hi, fa = f(a), fb = f(b);
   double c = a, fc = fa, d = b - a, e = d;
   const double eps = 2.220446049250313e-16;
-  for (int it = 0; it < 100; ++it) {
+  for (int it = 0; it < maxit; ++it) {
     if ((fb > 0.0) == (fc > 0.0)) {
       c = a; fc = fa; d = b - a; e = d;
     }
@@ -554,8 +559,12 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
             const double b = xi / eta;
             w = b / (1.0 + sqrt(1.0 - b * b));
           }
-          bool conv = false;
-          for (int it = 0; it < 30; ++it) {
+          const bool fixed = q.c2p_iters > 0;
+          // the recovery study's fixed-iteration solver starts from the middle of (0, 1)
+          if (fixed) w = 0.5;
+          const int cap = fixed ? q.c2p_iters : 30;
+          bool conv = fixed;
+          for (int it = 0; it < cap; ++it) {
             const double Pw = (((A * w - B) * w + C) * w - Dd) * w + A;
             const double dPw = ((4.0 * A * w - 3.0 * B) * w + 2.0 * C) * w - Dd;
             double wn = w - Pw / dPw;
@@ -563,7 +572,7 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
             else if (wn >= 1.0) wn = 0.5 * (w + 1.0);
             const double step = fabs(wn - w);
             w = wn;
-            if (step <= 1e-13 * wn) { conv = true; break; }
+            if (!fixed && step <= 1e-13 * wn) { conv = true; break; }
           }
           if (!conv) status = C2P_NOCONV;
         }
@@ -622,7 +631,8 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
           } else {
             double hi = 200.0 * 200.0 - 1.0;
             for (int k = 0; k < 60 && (((hi + c1) * hi + c2) * hi + c3) < 0.0; ++k) hi *= 4.0;
-            if (!tm_brent_root(c1, c2, c3, 0.0, hi, Wc)) status = C2P_NOCONV;
+            if (!tm_brent_root(c1, c2, c3, 0.0, hi, Wc, q.c2p_iters > 0 ? q.c2p_iters : 100) && q.c2p_iters == 0)
+              status = C2P_NOCONV;
           }
         } else {
           // analytic (trigonometric / Cardano), then one Newton step on the cubic

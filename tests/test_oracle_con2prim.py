@@ -168,3 +168,154 @@ def test_failure_convention(eos):
     assert status.tolist() == [0, 1, 1, 1]
     assert torch.all(W[0, 1:] == cp.RHO_FLOOR) and torch.all(W[-1, 1:] == cp.P_FLOOR)
     assert torch.all(W[1:-1, 1:] == 0) and torch.isfinite(W).all()
+
+
+# ---------------------------------------------------------------- fixed iteration counts
+# (the solvers of the recovery study, Sec. 3.3)
+
+def _grid_U(eos):
+    c = 3.0e8
+    G, PP = wl.c2p_grid(25, c=c)
+    g, P = G.ravel(), PP.ravel()
+    beta = np.sqrt((1 - 1 / g) * (1 + 1 / g))
+    st = Setup(dim=3, p=0, eos=eos, c=c)
+    v = np.stack([beta * c, 0 * g, 0 * g])
+    U = srhd.prim3_to_cons(torch.tensor(1.0 / g), torch.tensor(v), torch.tensor(P), st)
+    return st, U, beta * c
+
+
+def _tm_cubics(n, seed):
+    rng = np.random.default_rng(seed)
+    rho, v, P = _states(rng, n, 100.0, 1e-4, 1e3)
+    st = Setup(dim=3, p=0, eos=TM)
+    U = srhd.prim3_to_cons(*(torch.tensor(a) for a in (rho, v, P)), st)
+    ok, D, S, tau, Smag, nhat, xi, t = cp._prep(U, st)
+    c1, c2, c3 = cp._tm_coeffs(xi, 1.0 + t)
+    return [(float(a), float(b), float(cc)) for a, b, cc in zip(c1, c2, c3)]
+
+
+def test_brent_steps_matches_scipy_brentq_at_convergence():
+    """Run to convergence, the oracle's own Brent iteration lands on the root scipy's brentq
+    finds (both stop within a few ulps of it)."""
+    from scipy.optimize import brentq
+    eps = np.finfo(float).eps
+    for c1, c2, c3 in _tm_cubics(200, 5):
+        f = (lambda W: ((W + c1) * W + c2) * W + c3)
+        hi = 200.0 ** 2 - 1.0
+        while f(hi) < 0:
+            hi *= 4.0
+        mine = cp.brent_steps(f, 0.0, hi, 200)
+        ref = brentq(f, 0.0, hi, xtol=1e-300, rtol=4 * eps, maxiter=200)
+        assert abs(mine - ref) <= 16 * eps * abs(ref), (c1, c2, c3, mine, ref)
+
+
+def test_brent_steps_iterates_equal_scipy_brentq_at_every_cap():
+    """scipy's brentq stopped after k steps (maxiter=k, no error) returns its current
+    iterate: the oracle's Brent iteration stopped after k steps lands on the same point,
+    for every k from 1 to 24 on 50 cubics of the recovery (same decisions at every step)."""
+    from scipy.optimize import brentq
+    eps = np.finfo(float).eps
+    for c1, c2, c3 in _tm_cubics(50, 7):
+        f = (lambda W: ((W + c1) * W + c2) * W + c3)
+        hi = 200.0 ** 2 - 1.0
+        while f(hi) < 0:
+            hi *= 4.0
+        for k in range(1, 25):
+            mine = cp.brent_steps(f, 0.0, hi, k)
+            ref = brentq(f, 0.0, hi, xtol=1e-300, rtol=4 * eps, maxiter=k, disp=False)
+            assert abs(mine - ref) <= 4 * eps * abs(ref), (k, mine, ref)
+
+
+def test_brent_steps_keep_a_bracket_and_converge_within_the_bisection_bound():
+    """At every step f(b) and f(c) do not share a sign (the root stays bracketed by the best
+    iterate b and the other end c), and convergence takes at most (bits of the bracket)^2
+    steps, Brent's guarantee against bisection's (bits) steps."""
+    eps = np.finfo(float).eps
+    steps, nbits = [], []
+    for c1, c2, c3 in _tm_cubics(100, 6):
+        f = (lambda W: ((W + c1) * W + c2) * W + c3)
+        hi = 200.0 ** 2 - 1.0
+        while f(hi) < 0:
+            hi *= 4.0
+        hist = []
+        root = cp.brent_steps(f, 0.0, hi, 10000, history=hist)
+        for b, c, fb, fc in hist:
+            assert fb == 0.0 or (fb > 0) != (fc > 0)
+            assert abs(fb) <= abs(fc)
+        bits = np.log2(hi / (eps * max(root, 1e-300))) + 1
+        assert len(hist) <= bits * bits
+        steps.append(len(hist))
+        nbits.append(bits)
+        # and it finishes on a bracket of a few ulps
+        b, c = hist[-1][0], hist[-1][1]
+        assert hist[-1][2] == 0.0 or abs(c - b) <= 8 * eps * abs(b)
+    # on these smooth cubics the interpolation steps carry the convergence: far fewer
+    # steps than bisection's one per bit of the bracket
+    assert np.median(steps) <= 0.4 * np.median(nbits), (np.median(steps), np.median(nbits))
+
+
+def test_brent_fixed_steps_error_shrinks_to_the_converged_root():
+    """The TM recovery with at most N Brent steps: on the paper's grid the velocity error
+    after 50 steps is no larger than after 25, and 100 steps reproduce the solver run
+    to convergence to rounding."""
+    st, U, vex = _grid_U(TM)
+    errs = {}
+    for n in (25, 50, 100):
+        st.c2p_iters = n
+        W, status = cp.con2prim(U, st, BRENT)
+        assert int((status != 0).sum()) == 0
+        u = W[1]
+        v = u / torch.sqrt(1 + (W[1:4] ** 2).sum(0) / st.c ** 2)
+        nz = vex > 0
+        errs[n] = np.abs((v.numpy() - vex)[nz] / vex[nz])
+    st.c2p_iters = 0
+    W_conv, _ = cp.con2prim(U, st, BRENT)
+    st.c2p_iters = 100
+    W100, _ = cp.con2prim(U, st, BRENT)
+    # the velocity (the study's quantity; the pressure of these cold states, Theta/c^2
+    # down to 1e-12, moves far more than its rounding when W moves by one ulp)
+    nz = vex > 0
+    du = ((W100[1] - W_conv[1]).abs()[nz] / W_conv[1].abs()[nz]).max()
+    assert float(du) <= 1e-14
+    assert np.all(errs[50] <= np.maximum(errs[25], 1e-15))
+    assert np.median(errs[25]) > np.median(errs[50]) or np.median(errs[25]) < 1e-14
+
+
+def test_fixed_newton_steps_converge_quadratically():
+    """The ideal-gas recovery with exactly N Newton steps from w = 1/2: on the paper's grid
+    the velocity error falls monotonically with N down to rounding, quadratically once
+    small (e_{N+1} <= 1e4 e_N^2 in the velocity error), 30 steps reproduce the solver run to convergence, and
+    the pattern the paper describes holds (Sec. 3.3: 6 steps recover the velocity near
+    machine precision below gamma = 10 and the error grows above; 12 steps reach it for
+    every gamma up to 100)."""
+    st, U, vex = _grid_U(IDEAL)
+    G, _ = wl.c2p_grid(25, c=st.c)
+    gam = G.ravel()
+    nz = vex > 0
+    st.c2p_iters = 0
+    W_conv, _ = cp.con2prim(U, st, NEWTON)
+    prev = None
+    e = {}
+    for n in range(1, 16):
+        st.c2p_iters = n
+        W, status = cp.con2prim(U, st, NEWTON)
+        assert int((status != 0).sum()) == 0
+        v = W[1] / torch.sqrt(1 + (W[1:4] ** 2).sum(0) / st.c ** 2)
+        e[n] = np.abs((v.numpy() - vex)[nz] / vex[nz])
+        if prev is not None:
+            # non-increasing down to the velocity's rounding floor (a few 1e-15 at gamma ~ 100)
+            assert np.all(e[n] <= np.maximum(prev * (1 + 1e-9), 1e-14))
+        prev = e[n]
+    for n in range(1, 15):
+        mask = (e[n] < 1e-3) & (e[n] > 1e-7)
+        assert np.all(e[n + 1][mask] <= 1e4 * e[n][mask] ** 2 + 1e-15)
+    g = gam[nz]
+    assert e[6][g < 10].max() < 1e-14 and e[6][g > 50].min() > 1e-10
+    assert e[12].max() < 1e-14
+    st.c2p_iters = 30
+    W30, _ = cp.con2prim(U, st, NEWTON)
+
+    def vel(W):
+        return W[1] / torch.sqrt(1 + (W[1:4] ** 2).sum(0) / st.c ** 2)
+    # the velocity (u = gamma v carries the conditioning 2 gamma^2 of gamma(w) at w -> 1)
+    assert float(((vel(W30) - vel(W_conv)).abs()[nz] / vel(W_conv).abs()[nz]).max()) <= 1e-14
