@@ -565,24 +565,28 @@ def fp32_contract(steps=50):
     s64.run(V64, cfg3["dt"], steps)
     s64.close()
     del s64, U64
-    cfg3, s32, U32 = _setup("kh_tm_fp32")
-    R32 = s32.rhs(U0)
-    t32 = _time_run(s32, U32, cfg3["dt"], steps, 5)
-    V32 = U0.clone()
-    s32.run(V32, cfg3["dt"], steps)
-    s32.close()
     d3 = wl.n_dof(cfg3)
     nv3 = R64.shape[0]
-    rhs_err = ((R32 - R64).reshape(nv3, -1).abs().max(1).values /
-               R64.reshape(nv3, -1).abs().max(1).values).max().item()
-    drift = ((V32 - V64).reshape(nv3, -1).abs().sum(1) / V64.reshape(nv3, -1).abs().sum(1)).max().item()
-    out = {
-        "workload": "kh_tm_fp32: 2D 512x512 elements p=3 TM EOS",
-        "value_fp32": d3 * steps * 3 / t32, "value_fp64": d3 * steps * 3 / t64,
-        "speedup": t64 / t32, "unit": "DOF-stage/s", "steps": steps,
-        "rhs_rel_err_vs_fp64_gpu": rhs_err, "l1_fp32_vs_fp64_gpu_after_steps": drift}
-    finals = {"fp32": V32.cpu(), "fp64": V64.cpu()}
-    del s32, U32, R64, R32, V64, V32, U0
+    out = {"workload": "kh_tm_fp32: 2D 512x512 elements p=3 TM EOS", "value_fp64": d3 * steps * 3 / t64,
+           "unit": "DOF-stage/s", "steps": steps}
+    finals = {"fp64": V64.cpu()}
+    # the FP32 form with its sweeps on the vector ALUs, then on the matrix cores
+    for prec, tag in ((wl.FP32_CONTRACT, "fp32"), (wl.FP32_MFMA, "fp32_mfma")):
+        cfg3, s32, U32 = _setup("kh_tm_fp32", precision=prec)
+        R32 = s32.rhs(U0)
+        t32 = _time_run(s32, U32, cfg3["dt"], steps, 5)
+        V32 = U0.clone()
+        s32.run(V32, cfg3["dt"], steps)
+        s32.close()
+        rhs_err = ((R32 - R64).reshape(nv3, -1).abs().max(1).values /
+                   R64.reshape(nv3, -1).abs().max(1).values).max().item()
+        drift = ((V32 - V64).reshape(nv3, -1).abs().sum(1) / V64.reshape(nv3, -1).abs().sum(1)).max().item()
+        sfx = "" if tag == "fp32" else "_mfma"
+        out.update({f"value_fp32{sfx}": d3 * steps * 3 / t32, f"speedup{sfx}": t64 / t32,
+                    f"rhs_rel_err_vs_fp64_gpu{sfx}": rhs_err, f"l1_fp32{sfx}_vs_fp64_gpu_after_steps": drift})
+        finals[tag] = V32.cpu()
+        del s32, U32, R32, V32
+    del R64, V64, U0
     return out, finals
 
 
@@ -813,6 +817,7 @@ def main(argv=None):
         out["wave1d"]["l1_gpu_vs_oracle"] = _l1_rel(c1_final, ref["wave1d"].reshape(c1_final.shape))
         U_c3 = ref["kh_tm_fp32"].reshape(finals["fp32"].shape)
         out["fp32_contract"]["l1_fp32_vs_oracle_fp64"] = _l1_rel(finals["fp32"], U_c3)
+        out["fp32_contract"]["l1_fp32_mfma_vs_oracle_fp64"] = _l1_rel(finals["fp32_mfma"], U_c3)
         out["fp32_contract"]["l1_fp64_vs_oracle_fp64"] = _l1_rel(finals["fp64"], U_c3)
         out["fp32_contract"]["note"] = ("L1 errors: max over conserved components of sum |U - U_ref| / sum |U_ref| "
                                         "after the steps, against the oracle's FP64 run from the same initial "

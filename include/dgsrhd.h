@@ -50,7 +50,7 @@ enum {
 enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1, DG_BC_REFLECT = 2, DG_BC_DIRICHLET = 3 };
 enum { DG_EOS_IDEAL = 0, DG_EOS_TM = 1 };
 enum { DG_C2P_DEFAULT = -1, DG_C2P_NEWTON = 0, DG_C2P_QUARTIC = 1, DG_C2P_CUBIC = 2, DG_C2P_BRENT = 3 };
-enum { DG_FP64 = 0, DG_FP32_CONTRACT = 1 };
+enum { DG_FP64 = 0, DG_FP32_CONTRACT = 1, DG_FP32_MFMA = 2 };
 enum { DG_FLUX_HLL = 0, DG_FLUX_HLLC = 1 };
 enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
 
@@ -78,7 +78,9 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * evaluates the volume (D-hat) and lift contractions in FP32 with FP32
  * accumulation, on deviations from an FP64 reference per line of nodes; the face
  * traces, the recovery, the fluxes, the numerical flux, the operator and the RK
- * combine stay FP64.  phys = 1 applies
+ * combine stay FP64.  precision = DG_FP32_MFMA (dim 2, p 3 only; DG_EINVAL
+ * elsewhere) is the same form with the volume sweeps on the matrix cores
+ * (v_mfma_f32_4x4x1f32, FP32 accumulation).  phys = 1 applies
  * the physicality-enforcing operator (Sec. 2.5) after every SSP-RK stage, with
  * relative margin phys_eps (0 selects 1e-12).  flux selects the numerical flux at
  * the faces (Sec. 2.4): DG_FLUX_HLL (0, the default when the field is zeroed) or

@@ -190,7 +190,9 @@ const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s) {
     return "ideal EOS needs the Newton or quartic solver";
   if (d.eos == DG_EOS_TM && d.c2p != DG_C2P_NEWTON && d.c2p != DG_C2P_CUBIC && d.c2p != DG_C2P_BRENT)
     return "TM EOS needs the Newton, cubic or Brent solver";
-  if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT) return "unknown precision";
+  if (d.precision != DG_FP64 && d.precision != DG_FP32_CONTRACT && d.precision != DG_FP32_MFMA)
+    return "unknown precision";
+  if (d.precision == DG_FP32_MFMA && !(d.dim == 2 && d.p == 3)) return "DG_FP32_MFMA is built for dim 2, p 3";
   if (d.flux != DG_FLUX_HLL && d.flux != DG_FLUX_HLLC) return "flux must be HLL or HLLC";
   if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
   if (d.c2p_iters < 0 || d.c2p_iters > 1000) return "c2p_iters must be in 0..1000";

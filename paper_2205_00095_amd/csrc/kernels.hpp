@@ -361,7 +361,10 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
 // tile's boundary faces itself (one launch, no primitive buffer); MODE_STAGE is one
 // SSP-RK stage.
 enum { MODE_RHS = 0, MODE_STAGE = 1, MODE_RHS_FUSED = 2 };
-enum { PREC_FP64 = 0, PREC_FP32 = 1 };
+// PREC_FP32: the volume and lift contractions in FP32 on the vector ALUs; PREC_FP32_MFMA:
+// the same with the volume sweeps on the matrix cores (2D, p = 3 only)
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32_MFMA = 2 };
+typedef float mfma_f32x4 __attribute__((ext_vector_type(4)));
 
 // Tile of elements handled by one workgroup of k_element: TX x TY x TZ elements,
 // one node per lane.  Faces inside the tile are evaluated once and shared by the
@@ -692,7 +695,8 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   __shared__ double sW[NV * NTP];
   __shared__ double sF[NV * NTP];
   __shared__ double sFh[NV * FPB];
-  __shared__ double sFref[(PREC == PREC_FP32) ? DIM * NV * EPB * NFP : 1];
+  __shared__ double sFref[(PREC != PREC_FP64) ? DIM * NV * EPB * NFP : 1];
+  static_assert(PREC != PREC_FP32_MFMA || (DIM == 2 && P == 3), "MFMA sweeps are built for 2D p = 3");
   __shared__ int sflag[(MODE == MODE_STAGE) ? NT : 1];
   __shared__ int svote[(NT + 63) / 64];
   // fused right-hand side: the primitives of the halo elements, recovered in the tile
@@ -775,6 +779,36 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
 #pragma unroll
         for (int aa = 0; aa < N1; ++aa) acc += t.dhat[id][aa] * sF[v * NTP + el * ES + line_node<DIM, N1>(d, pt, aa)];
         R[v] += m.two_dx[d] * acc;
+      }
+    } else if constexpr (PREC == PREC_FP32_MFMA) {
+      // The same deviations contracted on the matrix cores: v_mfma_f32_4x4x1f32 forms 16
+      // independent 4x4 outer products per wave and instruction, block b from lanes
+      // 4b..4b+3, row r from lane 4b+r (operand A), column c from lane 4b+c (operand B),
+      // the 4x4 result in lane 4b+c, one row per accumulator register.  With one node per
+      // lane (lane = 16 e + 4 j + i in a wave's four elements, 2D p = 3) a block is a line
+      // of nodes: rows are the 4 conserved variables (NV = 4), columns the 4 output nodes
+      // along the line, K runs over the 4 nodes of the line in four instructions.  Along x
+      // the line is the lane's own j and the result lands in the lane's own node; along y
+      // the block's line is the lane's i, the result lands in the transposed lane (16 e +
+      // 4 i + j) and one lane permute per variable brings it home.
+      const int lane = tid & 63;
+      const int qq = lane & 3, jl = (lane >> 2) & 3;
+      const int eb = el * ES;
+      const int n0 = d == 0 ? jl * 4 : jl;  // the block line's first node
+      const double ref = sF[qq * NTP + eb + n0];
+      mfma_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        const int na = d == 0 ? jl * 4 + aa : aa * 4 + jl;
+        const float A = (float)(sF[qq * NTP + eb + na] - ref);
+        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(A, t.dhat_f[qq][aa], acc, 0, 0, 0);
+      }
+      const int src = d == 0 ? lane : ((lane & ~15) | (qq << 2) | jl);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const float r = d == 0 ? acc[v] : __shfl(acc[v], src, 64);
+        Rf[v] += (float)m.two_dx[d] * r;
+        if (id == 0) sFref[((d * NV + v) * EPB + el) * NFP + pt] = F[v];
       }
     } else {
       // deviations from the line's first node, so only the variation along d enters FP32
@@ -915,7 +949,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
       }
     }
   }
-  if constexpr (PREC == PREC_FP32) {
+  if constexpr (PREC != PREC_FP64) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) R[v] = (double)Rf[v];
   }

@@ -38,6 +38,10 @@ hipError_t by_mode(int mode, int flux, const ElemArgs& a, hipStream_t s) {
 
 template <int DIM, int P, int EOS>
 hipError_t by_prec(int prec, int mode, int flux, const ElemArgs& a, hipStream_t s) {
+  if (prec == PREC_FP32_MFMA) {
+    if constexpr (DIM == 2 && P == 3) return by_mode<DIM, P, EOS, PREC_FP32_MFMA>(mode, flux, a, s);
+    return hipErrorInvalidValue;
+  }
   return prec == PREC_FP64 ? by_mode<DIM, P, EOS, PREC_FP64>(mode, flux, a, s)
                            : by_mode<DIM, P, EOS, PREC_FP32>(mode, flux, a, s);
 }

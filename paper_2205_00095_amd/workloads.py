@@ -32,7 +32,7 @@ import numpy as np
 PERIODIC, OUTFLOW, REFLECT, DIRICHLET = 0, 1, 2, 3
 EOS_IDEAL, EOS_TM = 0, 1
 C2P_NEWTON, C2P_QUARTIC, C2P_CUBIC, C2P_BRENT = 0, 1, 2, 3
-FP64, FP32_CONTRACT = 0, 1
+FP64, FP32_CONTRACT, FP32_MFMA = 0, 1, 2
 FLUX_HLL, FLUX_HLLC = 0, 1
 
 

@@ -63,6 +63,8 @@ def _desc(**over):
     {"bc": (3, 0, 0), "bc_state": {(0, 0): (-1.0, 0.0, 0.0, 0.0, 1.0), (0, 1): (1.0, 0.0, 0.0, 0.0, 1.0)}},
     {"bc": (3, 0, 0), "bc_state": {(0, 0): (1.0, 1.5, 0.0, 0.0, 1.0), (0, 1): (1.0, 0.0, 0.0, 0.0, 1.0)}},
     {"bc": (1, 0, 0), "bc_hi": (3, 0, 0)},                        # a Dirichlet end without its state
+    {"precision": 2},                                             # matrix-core sweeps exist for 2D p = 3 only
+    {"c2p_iters": -1},                                            # fixed iteration count out of range
 ])
 def test_invalid_descriptions_are_rejected_without_a_gpu(change):
     """Validation runs on the host before any device call; the checks read the fields the

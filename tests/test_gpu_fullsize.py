@@ -55,16 +55,20 @@ def test_fullsize_step_kh_tm():
     assert d["c2p_fail"] == 0 and d["flagged"] == 0 and d["trace_fallback"] == 0
 
 
-@pytest.mark.parametrize("kind,over", [("kh_tm_fp32", {}), ("kh_tm", {"n_elem": (12, 10, 1)}),
-                                       ("kh_ideal", {"n_elem": (10, 9, 1)}),
-                                       ("random3d", {"n_elem": (5, 4, 3)})])
-def test_fp32_contraction_rhs_error(kind, over):
-    cfg = wl.make_config(kind, precision=wl.FP32_CONTRACT, **over)
+@pytest.mark.parametrize("kind,over,prec", [("kh_tm_fp32", {}, wl.FP32_CONTRACT), ("kh_tm", {"n_elem": (12, 10, 1)}, wl.FP32_CONTRACT),
+                                            ("kh_ideal", {"n_elem": (10, 9, 1)}, wl.FP32_CONTRACT),
+                                            ("random3d", {"n_elem": (5, 4, 3)}, wl.FP32_CONTRACT),
+                                            ("kh_tm_fp32", {}, wl.FP32_MFMA), ("kh_tm", {"n_elem": (12, 10, 1)}, wl.FP32_MFMA),
+                                            ("kh_ideal", {"n_elem": (11, 9, 1), "p": 3}, wl.FP32_MFMA)])
+def test_fp32_contraction_rhs_error(kind, over, prec):
+    """FP32 form (sweeps on the vector ALUs, or on the matrix cores) against the FP64 oracle."""
+    cfg = wl.make_config(kind, **over)
+    cfg["precision"] = prec
     st, U = oracle_state(cfg)
     R_ref = odg.rhs(U, st)
     R = _solver(cfg).rhs(U.cuda()).cpu()
     err = rel_err_per_var(R, R_ref)
-    print(f"{kind} {over}: FP32-contraction RHS error {err.tolist()}", flush=True)
+    print(f"{kind} {over} precision {prec}: FP32-contraction RHS error {err.tolist()}", flush=True)
     assert float(err.max()) <= 1e-5, err.tolist()
 
 
@@ -100,3 +104,28 @@ def test_fp32_contraction_drift_kh():
     drift = ((A - B).abs().reshape(4, -1).sum(1) / A.abs().reshape(4, -1).sum(1)).cpu()
     print(f"FP32-contraction L1 drift after 50 steps: {drift.tolist()}", flush=True)
     assert float(drift.max()) < 1e-5
+
+
+def test_fp32_mfma_sweeps_equal_the_vector_sweeps_to_fp32_rounding():
+    """The matrix-core sweeps compute the same FP32 deviations as the vector ones; the two
+    forms differ only by FP32 rounding order: per component well inside 1e-6 of the RHS."""
+    cfg = wl.make_config("kh_tm", n_elem=(20, 12, 1))
+    st, U = oracle_state(cfg)
+    out = {}
+    for prec in (wl.FP32_CONTRACT, wl.FP32_MFMA, wl.FP64):
+        c = dict(cfg, precision=prec)
+        out[prec] = _solver(c).rhs(U.cuda()).cpu()
+    e_mv = rel_err_per_var(out[wl.FP32_MFMA], out[wl.FP32_CONTRACT])
+    e_m64 = rel_err_per_var(out[wl.FP32_MFMA], out[wl.FP64])
+    e_v64 = rel_err_per_var(out[wl.FP32_CONTRACT], out[wl.FP64])
+    print(f"MFMA vs vector sweeps {e_mv.tolist()}; vs FP64 {e_m64.tolist()} (vector: {e_v64.tolist()})", flush=True)
+    assert float(e_mv.max()) <= 1e-6
+    assert float(e_m64.max()) <= 2 * float(e_v64.max()) + 1e-7
+
+
+def test_fp32_mfma_is_rejected_off_its_shape():
+    from paper_2205_00095_amd.solver import Solver
+    cfg = wl.make_config("kh_ideal", n_elem=(4, 4, 1))
+    cfg["precision"] = wl.FP32_MFMA       # p = 2: no matrix-core sweeps for it
+    with pytest.raises(Exception):
+        Solver(cfg)
