@@ -772,6 +772,7 @@ def main(argv=None):
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": prof["traffic_bytes_per_launch"] if prof else None,
             "kernel": "k_element stage (one SSP-RK3 stage)",
+            "dg_rhs_frac": 2 * nvar * 8.0 * dofs / t_rhs / 1e9 / HBM_PEAK_GBS,
             "stage_us": stage_s * 1e6, "con2prim_us": t_c2p * 1e6,
             "bytes_per_dof": _stage_bytes_per_dof(nvar),
             "algorithmic_bytes_per_launch": bytes_per_launch,
