@@ -223,6 +223,49 @@ def sound_primitives(cfg: dict, t: float = 0.0, amp: float = 1e-6):
     return rho, v, P
 
 
+def wave_frame(dim: int):
+    """Unit wave vector and transverse directions of the linear-wave tests (Sec. 4): in 3D
+    the rotation of the paper about a = (0, -1, 1)/sqrt(2) by theta = atan(sqrt(2)) (its
+    wave-angle formula with N = 3, n = 2) applied to e_x, e_y, e_z (e_x goes to the body
+    diagonal); in 2D the in-plane diagonal and its in-plane normal; in 1D e_x."""
+    if dim == 1:
+        return np.array([1.0]), []
+    if dim == 2:
+        return np.array([1.0, 1.0]) / np.sqrt(2.0), [np.array([-1.0, 1.0]) / np.sqrt(2.0)]
+    a = np.array([0.0, -1.0, 1.0]) / np.sqrt(2.0)
+    th = np.arctan(np.sqrt(2.0))
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    R = np.cos(th) * np.eye(3) + (1.0 - np.cos(th)) * np.outer(a, a) + np.sin(th) * K
+    return R[:, 0], [R[:, 1], R[:, 2]]
+
+
+def zero_mode_primitives(cfg: dict, mode: str, amp: float = 1e-6):
+    """The linear waves of zero speed at rest (rho0 = P0 = 1, phase k.x with k = 2 pi
+    times the diagonal of the unit cell, as sound_primitives): 'entropy' (the 0^(1)
+    family: rho = rho0 + amp sin(k.x), v = 0, P = P0) and 'shear2' / 'shear3' (0^(2),
+    0^(3): v = amp sin(k.x) t with t the first / second transverse direction of
+    wave_frame, rho = rho0, P = P0).  A density profile at rest under uniform pressure,
+    and a parallel shear flow with uniform density and pressure (its velocity normal to
+    the direction it varies in, so it carries no mass or momentum across the planes of
+    constant phase), are exact stationary solutions of the full equations: the exact
+    solution at every time is the initial state."""
+    coords = node_coords(cfg)
+    dim = cfg["dim"]
+    k = np.full(dim, 2.0 * np.pi)
+    phase = sum(k[d] * coords[d] for d in range(dim))
+    w = amp * np.sin(phase)
+    rho = np.ones_like(w)
+    P = np.ones_like(w)
+    v = np.zeros((dim,) + w.shape)
+    if mode == "entropy":
+        rho = rho + w
+    else:
+        _, ts = wave_frame(dim)
+        t = ts[0] if mode == "shear2" else ts[1]
+        v = np.stack([w * t[d] for d in range(dim)])
+    return rho, v, P
+
+
 def sound_period(cfg: dict) -> float:
     """Time for the sound wave of sound_primitives to travel one wavelength."""
     gam = cfg["gamma_ad"]
@@ -273,6 +316,8 @@ def initial_primitives(cfg: dict, seed: int | None = None):
         return kh_paper_primitives(cfg)
     if init == "sound":
         return sound_primitives(cfg)
+    if init in ("entropy", "shear2", "shear3"):
+        return zero_mode_primitives(cfg, init)
     raise ValueError(f"unknown init {init!r}")
 
 

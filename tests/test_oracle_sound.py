@@ -51,3 +51,57 @@ def test_sound_wave_eigenvector_is_a_linear_mode():
     R = dg.rhs(U(0.0), st)
     rel = float((R - dUdt).abs().max() / dUdt.abs().max())
     assert rel < 1e-4, rel
+
+
+# ------------------------------------------- the zero-speed families (entropy, shear)
+
+def _max_rhs(mode, N, p, dim, comp):
+    from oracle import dg
+    cfg = wl.make_config("sound", dim=dim, p=p, n_elem=tuple([N] * dim + [1] * (3 - dim)), init=mode)
+    st = Setup.from_config(cfg)
+    U0 = srhd.prim3_to_cons(*(torch.tensor(a) for a in wl.initial_primitives(cfg)), st)
+    U0 = U0.reshape((st.nvar,) + wl.field_shape(cfg))
+    return float(dg.rhs(U0, st)[comp].abs().max())
+
+
+@pytest.mark.parametrize("mode,dim,comp", [("entropy", 2, 0), ("shear2", 2, 1), ("shear2", 3, 2),
+                                           ("shear3", 3, 3), ("entropy", 3, 0)])
+def test_zero_speed_modes_are_stationary(mode, dim, comp):
+    """The entropy and shear waves of zero speed (the paper's 0^(1), 0^(2), 0^(3) cases at
+    rest) are exact stationary solutions: the oracle's RHS of their nodal interpolant is
+    only the discretisation error, falling at order >= 1.8 with the mesh (p = 1, 2)."""
+    for p in (1, 2):
+        r = [_max_rhs(mode, N, p, dim, comp) for N in (8, 16)]
+        rate = math.log2(r[0] / r[1])
+        assert rate >= 1.8, (mode, dim, p, r)
+
+
+def test_wave_frame_is_the_papers_rotation():
+    """The 3D wave direction is the body diagonal (the paper's rotation of e_x) and the two
+    transverse directions with it form an orthonormal frame."""
+    import numpy as np
+    k, ts = wl.wave_frame(3)
+    assert np.allclose(k, np.ones(3) / np.sqrt(3.0))
+    M = np.stack([k] + ts)
+    assert np.allclose(M @ M.T, np.eye(3))
+    k2, t2 = wl.wave_frame(2)
+    assert abs(float(k2 @ t2[0])) < 1e-15 and abs(np.linalg.norm(t2[0]) - 1) < 1e-15
+
+
+def test_a_longitudinal_velocity_perturbation_is_not_stationary():
+    """Contrast for the shear pin: the same perturbation along the wave vector compresses
+    the gas (it is a sum of sound waves) and its RHS does not vanish with the mesh."""
+    from oracle import dg
+    import numpy as np
+    r = []
+    for N in (8, 16):
+        cfg = wl.make_config("sound", dim=2, p=2, n_elem=(N, N, 1), init="shear2")
+        st = Setup.from_config(cfg)
+        rho, v, P = wl.initial_primitives(cfg)
+        k, ts = wl.wave_frame(2)
+        amp_sin = v[0] / ts[0][0]
+        v = np.stack([amp_sin * k[0], amp_sin * k[1]])
+        U0 = srhd.prim3_to_cons(torch.tensor(rho), torch.tensor(v), torch.tensor(P), st)
+        U0 = U0.reshape((st.nvar,) + wl.field_shape(cfg))
+        r.append(float(dg.rhs(U0, st)[0].abs().max()))
+    assert r[1] > 0.8 * r[0] and r[1] > 1e-6, r
