@@ -46,6 +46,10 @@ RHS_CASES = [
     ("random3d", {"n_elem": (5, 4, 3)}),
     ("random3d", {"n_elem": (4, 3, 3), "p": 1, "eos": wl.EOS_TM, "c2p": wl.C2P_CUBIC}),
     ("random3d", {"n_elem": (3, 3, 2), "p": 3}),
+    # SI units (c = 3e8 m/s, P = c^2, v = 0.25 c): the same flow at magnitudes up to
+    # c^4 ~ 1e34, for the reduced-precision division and root forms the build uses
+    ("kh_paper", {"nx": 6, "p": 2, "c": 3.0e8}),
+    ("kh_paper", {"nx": 5, "p": 3, "c": 3.0e8, "eos": wl.EOS_TM, "c2p": wl.C2P_NEWTON}),
 ]
 
 
@@ -214,7 +218,10 @@ def test_enforce_matches_oracle(dim, p, n_elem):
                                               ("kh_tm", {"n_elem": (10, 7, 1), "c": 2.0}, 3),
                                               ("kh_ideal", {"n_elem": (10, 9, 1)}, 5),
                                               ("wave1d", {}, 10),
-                                              ("random3d", {"n_elem": (5, 4, 3)}, 1)])
+                                              ("random3d", {"n_elem": (5, 4, 3)}, 1),
+                                              ("kh_paper", {"nx": 6, "p": 2, "c": 3.0e8}, 3),
+                                              ("kh_paper", {"nx": 5, "p": 3, "c": 3.0e8, "eos": wl.EOS_TM,
+                                                            "c2p": wl.C2P_NEWTON}, 3)])
 def test_ssprk3_steps_match_oracle(kind, over, nsteps):
     cfg = _case_cfg(kind, over)
     st, U = oracle_state(cfg)
