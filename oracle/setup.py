@@ -26,6 +26,7 @@ class Setup:
     phys_eps: float = 1e-12
     flux: int = HLL          # numerical flux: HLL or HLLC (Sec. 2.4)
     c2p_iters: int = 0       # > 0: fixed iteration count of the iterative recovery solvers (Sec. 3.3)
+    limiter: int = 0         # 1: the minmod slope limiter after every stage, before the operator
     extra: dict = field(default_factory=dict)
 
     @staticmethod
@@ -34,7 +35,8 @@ class Setup:
                      hi=tuple(cfg["hi"]), bc=tuple(cfg["bc"]), eos=cfg["eos"],
                      gamma_ad=cfg["gamma_ad"], c=cfg["c"], c2p=cfg["c2p"],
                      flux=cfg.get("flux", HLL), bc_hi=tuple(cfg.get("bc_hi", (0, 0, 0))),
-                     bc_state=dict(cfg.get("bc_state", {})), c2p_iters=int(cfg.get("c2p_iters", 0)))
+                     bc_state=dict(cfg.get("bc_state", {})), c2p_iters=int(cfg.get("c2p_iters", 0)),
+                     limiter=int(cfg.get("limiter", 0)))
 
     @property
     def nvar(self) -> int:

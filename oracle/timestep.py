@@ -8,6 +8,9 @@ Reading: the paper does not place the operator; it is applied after every
 stage, so each stage stays a convex combination of admissible forward-Euler
 states.  The step is fixed: dt = 0.1/(2p+1) min_d dx_d / c.
 
+With Setup.limiter the slope limiter (oracle/limiter.py) acts on every stage
+output before the operator: Pi(Lim(.)).
+
 Lower orders (the paper pairs basis orders 0, 1, 2 with RK1, SSPRK2, SSPRK3 in
 its convergence and performance runs, Sec. 2.3 citing the Shu-Osher schemes):
 RK1 is forward Euler, U^+ = Pi(U + dt L(U)); SSPRK2 is
@@ -20,7 +23,7 @@ density wave (p = 2 with SSPRK3; p = 0 with RK1 and p = 1 with SSPRK2).
 """
 from __future__ import annotations
 
-from . import dg, physicality
+from . import dg, limiter, physicality
 
 
 def ssprk3(U, dt, L, P=lambda v: v):
@@ -44,9 +47,10 @@ SCHEMES = {1: rk1, 2: ssprk2, 3: ssprk3}
 def step(U, dt, st, phys=True, stats=None, order=3):
     L = lambda V: dg.rhs(V, st, stats)  # noqa: E731
     scheme = SCHEMES[order]
+    lim = (lambda V: limiter.limit(V, st, stats)) if getattr(st, "limiter", 0) else (lambda V: V)
     if phys:
-        return scheme(U, dt, L, lambda V: physicality.enforce(V, st, stats))
-    return scheme(U, dt, L)
+        return scheme(U, dt, L, lambda V: physicality.enforce(lim(V), st, stats))
+    return scheme(U, dt, L, lim)
 
 
 def run(U, dt, nsteps, st, phys=True, stats=None, order=3):
