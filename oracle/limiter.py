@@ -2,33 +2,45 @@
 
 The paper stabilises its p >= 1 shock runs with a slope limiter beside the
 physicality operator (Sec. 2.3, naming the minmod limiter of van Leer 1979 and
-the limiter of Moe, Rossmanith & Seal 2015; Sec. 4 uses them in its 1D Riemann
-problems) but prints neither algorithm.
+the limiter of Moe, Rossmanith & Seal 2015; Sec. 4 uses the latter in its 1D
+Riemann problems) but prints neither algorithm.
 
-Reading R29: the componentwise minmod slope limiter of DG schemes in the
-gradient (MUSCL) form, applied to every conserved component of every element:
-  * average  u_bar = sum_i w_i u_i / sum_i w_i  (tensor Gauss-Legendre weights);
-  * slope along d, the amplitude of the element's linear mode in xi_d (its L2
-    projection onto xi_d on the reference element [-1, 1]^dim):
-        s_d = sum_i w_i xi_{d,i} u_i / sum_i w_i xi_{d,i}^2,
+Reading R29: minmod-bounded slopes applied in scaling form, per element:
+  * averages  u_bar_k = sum_i w_i u_{k,i} / sum_i w_i  (tensor Gauss-Legendre weights)
+    of every conserved component k;
+  * slope of component k along d, the coefficient of xi_d in the element's
+    Legendre expansion (its L2 projection onto xi_d on [-1, 1]^dim):
+        s = sum_i w_i xi_{d,i} u_{k,i} / sum_i w_i xi_{d,i}^2,
     summed over mirror pairs of nodes (xi_{d,i} = -xi_{d,m}, equal weights) as
-    w_i xi_{d,i} (u_i - u_m) / 2, so that a constant element has slope exactly 0;
-  * limited slope  s~_d = minmod(s_d, (u_bar_{d+} - u_bar)/2, (u_bar - u_bar_{d-})/2),
-    u_bar_{d+-} the averages of the neighbours along d (periodic wrap; at a
-    non-periodic end the element's own average, so the slope there is zero);
-    half the difference because the centres are one element width apart while s
-    is the change from the centre to the face; minmod is the argument of least
-    magnitude when all have one sign, else 0;
-  * if s~_d = s_d for every d the component is left as it is, else it becomes the
-    linear function u_bar + sum_d s~_d xi_d (higher modes dropped).
-The average is unchanged either way (the limiter conserves).  Applied after each
-SSP-RK stage, before the physicality operator.
+    w_i xi_{d,i} (u_{k,i} - u_{k,m}) / 2, so that a constant element has slope 0;
+  * the minmod bound of that slope by the differences to the neighbours' averages
+    along d (Cockburn & Shu's generalized slope limiter: s measures the change from
+    the centre to the face, bounded by the full differences):
+        s~ = minmod(s, u_bar_{d+} - u_bar, u_bar - u_bar_{d-}),
+    periodic wrap; at a non-periodic end the element's own average (difference 0);
+    minmod is the argument of least magnitude when all have one sign, else 0;
+  * one factor for the whole element, the least ratio s~ / s over components and
+    directions, counting only pairs where the bound moves the slope by more than
+    EPS times the component's scale (the element's average energy
+    E = |tau_bar + D_bar c^2| over c^2 for D, over c for S, E for tau), so that
+    rounding noise in a flat component does not flatten the others:
+        theta = min(1, min over those pairs of s~ / s);
+  * where theta < 1 every node moves towards the average:
+        u_i <- u_bar + theta (u_i - u_bar)   (all components, all modes).
+Averages are unchanged (the limiter conserves).  With one factor for all
+components every node stays on the segment between itself and the average, so an
+element whose nodes and average are admissible stays admissible (the admissible
+set is convex); the componentwise form (each component replaced by its limited
+linear function) lost that and gave an inadmissible average within the first step
+of the strong blast wave (problem 2) at p = 1.  Applied after each SSP-RK stage,
+before the physicality operator.
 
-Pinned by tests/test_oracle_limiter.py: averages preserved, linear data left
-unchanged, a jump inside an element cut back to a constant, the minmod bounds
+Pinned by tests/test_oracle_limiter.py: the slope against numpy's Legendre
+fit, averages preserved, linear data left unchanged, a jump inside an element
+scaled to the neighbour difference, a spike cut to a constant, the minmod bounds
 and sign agreement of every limited slope, idempotence, and total variation of
-the averages not increasing over a limited forward-Euler step on a Riemann
-problem.
+the averages not increasing over limited forward-Euler steps on a Riemann problem
+(while it grows without the limiter).
 """
 from __future__ import annotations
 
@@ -37,6 +49,8 @@ import torch
 from . import basis
 from .dg import elem_weights
 from .setup import PERIODIC
+
+EPS = 1e-10
 
 
 def _minmod(a, b, c):
@@ -74,28 +88,43 @@ def _neighbour_average(avg, d, side, st):
     return nb
 
 
+def averages(U, st):
+    w = elem_weights(st)
+    return (U * w).sum((4, 5, 6)) / w.sum()
+
+
+def scales(avg, st):
+    """Per-component scale of each element: E/c^2 (D), E/c (S), E (tau), E = |tau + D c^2|."""
+    c = st.c
+    E = (avg[-1] + avg[0] * c * c).abs()
+    return torch.stack([E / (c * c)] + [E / c] * st.dim + [E])
+
+
+def theta(U, st):
+    """Scaling factor of every element [nez, ney, nex]."""
+    w = elem_weights(st)
+    avg = averages(U, st)
+    sig = scales(avg, st)
+    th = torch.ones(avg.shape[1:], dtype=torch.float64)
+    for d in range(st.dim):
+        s = _slope(U, w, _xi(st, d), d)
+        sl = _minmod(s, _neighbour_average(avg, d, +1, st) - avg, avg - _neighbour_average(avg, d, -1, st))
+        act = (s - sl).abs() > EPS * sig
+        ratio = torch.where(act, sl / torch.where(act, s, torch.ones_like(s)), torch.ones_like(s))
+        th = torch.minimum(th, ratio.min(0).values)
+    return th
+
+
 def limit(U, st, stats=None):
     """Apply the slope limiter to every element of U [nvar, nez, ney, nex, nk, nj, ni]."""
     if st.p == 0:
         return U
-    w = elem_weights(st)
-    wsum = w.sum()
-    avg = (U * w).sum((4, 5, 6)) / wsum                      # [nvar, nez, ney, nex]
-    slopes, limited = [], []
-    for d in range(st.dim):
-        xi = _xi(st, d)
-        s = _slope(U, w, xi, d)
-        fwd = 0.5 * (_neighbour_average(avg, d, +1, st) - avg)
-        bwd = 0.5 * (avg - _neighbour_average(avg, d, -1, st))
-        sl = _minmod(s, fwd, bwd)
-        slopes.append(sl)
-        limited.append(sl != s)
-    changed = limited[0]
-    for m in limited[1:]:
-        changed = changed | m                                  # [nvar, nez, ney, nex]
+    th = theta(U, st)
+    lim = th < 1.0
     if stats is not None:
-        stats["limited"] = stats.get("limited", 0) + int(changed.sum())
-    if not bool(changed.any()):
+        stats["limited"] = stats.get("limited", 0) + int(lim.sum())
+    if not bool(lim.any()):
         return U
-    lin = avg[..., None, None, None] + sum(slopes[d][..., None, None, None] * _xi(st, d) for d in range(st.dim))
-    return torch.where(changed[..., None, None, None], lin, U)
+    avg = averages(U, st)[..., None, None, None]
+    scaled = avg + th[None, ..., None, None, None] * (U - avg)
+    return torch.where(lim[None, ..., None, None, None], scaled, U)

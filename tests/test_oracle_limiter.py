@@ -90,20 +90,28 @@ def test_periodic_linear_modes_only_limited_at_the_wrap():
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
-def test_a_jump_inside_an_element_takes_the_neighbour_difference_as_slope(p):
-    """A step from 1 to 3 whose jump lies inside element 4 of 10: its own slope is steeper
-    than half the difference to either constant neighbour, so the element becomes the
-    linear function with that half-difference as slope; the constant elements stay."""
+def test_a_jump_inside_an_element_is_scaled_to_the_neighbour_difference(p):
+    """A step from 1 to 3 whose jump lies inside element 4 of 10: its slope (the linear
+    Legendre coefficient, from numpy's fit) is steeper than the difference to either
+    constant neighbour, so the element's deviation from its average is scaled by the
+    least ratio bound / slope over the components; the constant elements stay."""
+    from numpy.polynomial import legendre as L
     st = Setup(dim=1, p=p, n_elem=(10, 1, 1), bc=(OUTFLOW, OUTFLOW, OUTFLOW))
     x = _node_x(st, 0)
     f = torch.where(x < 0.45, torch.ones_like(x), 3.0 * torch.ones_like(x))
     U = _field(st, f)
     V = limiter.limit(U, st)
     avg = _averages(U, st)[:, 0, 0]
-    xi = limiter._xi(st, 0)[0, 0, 0, 0]
+    xs = basis.tables(p)["x"]
+    ratios = []
     for k in range(st.nvar):
-        half = 0.5 * min(float(avg[k, 5] - avg[k, 4]), float(avg[k, 4] - avg[k, 3]))
-        assert torch.allclose(V[k, 0, 0, 4], avg[k, 4] + half * xi, rtol=0, atol=1e-14)
+        slope = L.legfit(xs, U[k, 0, 0, 4, 0, 0].numpy(), p)[1]
+        bound = min(float(avg[k, 5] - avg[k, 4]), float(avg[k, 4] - avg[k, 3]))
+        assert 0 < bound < slope
+        ratios.append(bound / slope)
+    th = min(ratios)
+    for k in range(st.nvar):
+        assert torch.allclose(V[k, 0, 0, 4], avg[k, 4] + th * (U[k, 0, 0, 4] - avg[k, 4]), rtol=0, atol=1e-13)
     assert torch.equal(V[:, :, :, :4], U[:, :, :, :4]) and torch.equal(V[:, :, :, 5:], U[:, :, :, 5:])
 
 
@@ -122,39 +130,46 @@ def test_a_spike_inside_an_element_is_cut_to_a_constant(p):
     assert torch.equal(V[:, :, :, :4], U[:, :, :, :4]) and torch.equal(V[:, :, :, 5:], U[:, :, :, 5:])
 
 
-@pytest.mark.parametrize("dim,p", [(1, 2), (2, 1), (2, 3)])
+@pytest.mark.parametrize("dim,p", [(1, 2), (2, 1), (2, 3), (3, 1)])
 def test_limited_slopes_obey_the_minmod_bounds(dim, p):
-    """On random data: every element's limited slope along each direction has the sign of
-    its slope and of both half-differences of the averages (or is zero), and no larger
-    magnitude than any of them; averages kept; limiting twice changes nothing more."""
+    """On random data: each element moves towards its average by one factor theta in
+    [0, 1] for all components; every limited slope keeps the sign of its own slope and
+    no larger magnitude, and stays within the minmod bound of the neighbour differences
+    (up to the rounding guard); averages kept; limiting twice changes nothing more."""
     rng = np.random.default_rng(8)
-    st = Setup(dim=dim, p=p, n_elem=(7, 6 if dim == 2 else 1, 1), bc=(PERIODIC,) * 3)
-    U = torch.from_numpy(rng.normal(size=(st.nvar,) + st.shape())) + 3.0
+    n = (7, 6 if dim > 1 else 1, 5 if dim > 2 else 1)
+    st = Setup(dim=dim, p=p, n_elem=n, bc=(PERIODIC,) * 3)
+    U = torch.from_numpy(rng.normal(size=(st.nvar,) + st.shape())) * 0.3 + 3.0
     V = limiter.limit(U, st)
-    assert torch.allclose(_averages(V, st), _averages(U, st), rtol=0, atol=1e-13)
-    w = odg.elem_weights(st)
     avg = _averages(U, st)
+    assert torch.allclose(_averages(V, st), avg, rtol=0, atol=1e-13)
+    # one factor per element: V - avg = theta (U - avg)
+    dU, dV = U - avg[..., None, None, None], V - avg[..., None, None, None]
+    th = (dV * dU).sum((0, 4, 5, 6)) / (dU * dU).sum((0, 4, 5, 6))
+    assert bool(((th >= -1e-14) & (th <= 1 + 1e-14)).all()) and float((th < 1 - 1e-12).float().mean()) > 0.3
+    assert torch.allclose(dV, th[None, ..., None, None, None] * dU, rtol=0, atol=1e-13)
+    w = odg.elem_weights(st)
+    sig = limiter.scales(avg, st)
     for d in range(dim):
         xi = limiter._xi(st, d)
         s = limiter._slope(U, w, xi, d)
         sv = limiter._slope(V, w, xi, d)
         ea = 3 - d
-        fwd = 0.5 * (torch.roll(avg, -1, ea) - avg)
-        bwd = 0.5 * (avg - torch.roll(avg, 1, ea))
-        for ref in (s, fwd, bwd):
-            ok = (sv == 0) | ((torch.sign(sv) == torch.sign(ref)) & (sv.abs() <= ref.abs() * (1 + 1e-12)))
-            # components left unchanged keep their own slope, which need not obey the bounds
-            unchanged = (V == U).all(-1).all(-1).all(-1)
-            assert bool((ok | unchanged).all())
+        fwd = torch.roll(avg, -1, ea) - avg
+        bwd = avg - torch.roll(avg, 1, ea)
+        bound = limiter._minmod(s, fwd, bwd).abs()
+        assert bool(((sv == 0) | (torch.sign(sv) == torch.sign(s))).all())
+        assert bool((sv.abs() <= s.abs() * (1 + 1e-12)).all())
+        assert bool((sv.abs() <= bound * (1 + 1e-12) + 2 * limiter.EPS * sig).all())
     W = limiter.limit(V, st)
     assert torch.allclose(W, V, rtol=0, atol=1e-13)
 
 
 def test_limited_euler_step_does_not_increase_the_total_variation_of_averages():
-    """The paper's Sod-like Riemann problem 4 at p = 1 on 60 cells: one forward-Euler step
-    (CFL 0.1/3) followed by the limiter and the physicality operator does not increase the
-    total variation of the averages of D (the limited scheme is TVD in the means), while
-    the unlimited step does increase it."""
+    """The paper's Sod-like Riemann problem 4 at p = 1 on 60 cells: forward-Euler steps
+    (CFL 0.1/3), each followed by the limiter and the physicality operator, do not
+    increase the total variation of the averages of D beyond the rounding guard (the
+    limited scheme is TVD in the means here), while without the limiter it grows."""
     from tests._exact import riemann_problem
     L, R, gam, _, _ = riemann_problem(4)
     st = Setup(dim=1, p=1, n_elem=(60, 1, 1), bc=(OUTFLOW,) * 3, gamma_ad=gam, eos=IDEAL, flux=HLLC)
@@ -176,9 +191,30 @@ def test_limited_euler_step_does_not_increase_the_total_variation_of_averages():
     for _ in range(20):
         raw = U + dt * odg.rhs(U, st)
         U = ophys.enforce(limiter.limit(raw, st), st)
-        assert tv(U) <= tv0 * (1 + 1e-12)
+        # up to what the rounding guard lets through (measured <= 2e-10 per step)
+        assert tv(U) <= tv0 * (1 + 1e-8)
         tv0 = tv(U)
         tvn = tv(Un)
         Un = ophys.enforce(Un + dt * odg.rhs(Un, st), st)
-        grew = grew or tv(Un) > tvn * (1 + 1e-6)
+        grew = grew or tv(Un) > tvn * (1 + 1e-4)   # measured up to 6e-3 per step
     assert grew
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_strong_blast_stays_admissible_with_the_limiter(p):
+    """The paper's strong blast wave (problem 2, pressure ratio 1e5) at 50 cells: 60 limited
+    steps with the physicality operator keep every element average admissible and every
+    recovery successful (the componentwise form lost an average in the first step)."""
+    from oracle import timestep
+    from tests._exact import riemann_problem
+    L, R, gam, _, _ = riemann_problem(2)
+    st = Setup(dim=1, p=p, n_elem=(50, 1, 1), bc=(OUTFLOW,) * 3, gamma_ad=gam, eos=IDEAL, flux=HLLC, limiter=1)
+    x = _node_x(st, 0)
+    one = torch.ones_like(x)
+    pick = lambda a, b: torch.where(x < 0.5, a * one, b * one)  # noqa: E731
+    U = srhd.prim3_to_cons(pick(L[0], R[0]), pick(L[1], R[1])[None], pick(L[2], R[2]), st)
+    stats = {}
+    U = timestep.run(U, 0.1 / (2 * p + 1) / 50, 60, st, stats=stats, order=p + 1)
+    assert stats.get("c2p_fail", 0) == 0 and stats.get("bad_average", 0) == 0
+    assert stats["limited"] > 0
+    assert bool(srhd.admissible(U, st).all())
