@@ -52,6 +52,7 @@ enum { DG_EOS_IDEAL = 0, DG_EOS_TM = 1 };
 enum { DG_C2P_DEFAULT = -1, DG_C2P_NEWTON = 0, DG_C2P_QUARTIC = 1, DG_C2P_CUBIC = 2, DG_C2P_BRENT = 3 };
 enum { DG_FP64 = 0, DG_FP32_CONTRACT = 1, DG_FP32_MFMA = 2 };
 enum { DG_FLUX_HLL = 0, DG_FLUX_HLLC = 1 };
+enum { DG_LIMITER_NONE = 0, DG_LIMITER_MINMOD = 1 };
 enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
 
 /* Mesh and method description.  Cartesian mesh of n_elem[d] equal elements on
@@ -92,7 +93,18 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * steps started from w = 1/2, the middle of the interval every start converges from
  * (no convergence test), with the TM EOS and c2p = BRENT at most c2p_iters Brent
  * steps on the bracket [0, 200^2 - 1]; no failure is counted for stopping there.  Valid
- * range 0..1000 (DG_EINVAL outside). */
+ * range 0..1000 (DG_EINVAL outside).
+ * limiter = DG_LIMITER_MINMOD (p >= 1; ignored at p = 0) applies the slope limiter the
+ * paper pairs with the operator for its p >= 1 shock runs (Sec. 2.3 names the minmod
+ * limiter of van Leer 1979) after every SSP-RK stage, before the operator: per
+ * element and conserved component, the slope along each d (the coefficient of xi_d in
+ * the element's Legendre expansion, from mirror pairs of nodes) is replaced by the
+ * minmod of itself and half the differences of the neighbouring element averages
+ * (periodic wrap; a non-periodic end takes the element's own average); where any
+ * slope changed, the component becomes its average plus the limited linear part.
+ * Averages are kept.  Each stage then runs as separate launches (stage, averages,
+ * limiter with operator and recovery).  The taped stepping and step-adjoint
+ * entry points reject it (DG_EINVAL); dg_rhs and dg_rhs_vjp do not involve it. */
 typedef struct {
   int dim, p;
   int n_elem[3];
@@ -110,6 +122,7 @@ typedef struct {
   int bc_hi[3];
   double bc_state[3][2][5];
   int c2p_iters;
+  int limiter;
 } dg_mesh_desc;
 
 typedef struct {
@@ -121,6 +134,7 @@ typedef struct {
   long long bad_average;     /* flagged elements left unchanged (inadmissible average) */
   long long bad_input;       /* dg_set_state nodes rejected */
   long long first_bad_elem;  /* lowest element index with a recovery failure, or -1 */
+  long long limited;         /* (element, component) pairs replaced by the slope limiter */
 } dg_diag;
 
 /* Create a context for one mesh.  Validates desc, builds the basis tables on the

@@ -32,13 +32,14 @@ class MeshDesc(ctypes.Structure):
         ("bc_hi", ctypes.c_int * 3),
         ("bc_state", ctypes.c_double * 30),
         ("c2p_iters", ctypes.c_int),
+        ("limiter", ctypes.c_int),
     ]
 
 
 class Diag(ctypes.Structure):
     _fields_ = [(n, ctypes.c_longlong) for n in (
         "c2p_fail", "c2p_noconv", "trace_fallback", "flagged", "smoothed", "bad_average",
-        "bad_input", "first_bad_elem")]
+        "bad_input", "first_bad_elem", "limited")]
 
 
 _P = ctypes.c_void_p

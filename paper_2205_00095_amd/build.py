@@ -47,6 +47,7 @@ def _units():
     for d in (1, 2, 3):
         units.append(("launch.hip", f"launch_dim{d}.o", [f"-DDG_DIM={d}"]))
         units.append(("launch_adj.hip", f"launch_adj_dim{d}.o", [f"-DDG_DIM={d}"]))
+        units.append(("launch_lim.hip", f"launch_lim_dim{d}.o", [f"-DDG_DIM={d}"]))
     return units
 
 

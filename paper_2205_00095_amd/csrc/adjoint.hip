@@ -185,6 +185,13 @@ int step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_ne
   return hipcheck(c, L_vjp(c, VJP_STAGE, a), what);
 }
 
+// The stepping adjoints differentiate the stage without the slope limiter.
+int reject_limiter(dg_ctx* c, const char* what) {
+  if (c->desc.limiter != DG_LIMITER_NONE)
+    return fail(c, DG_EINVAL, "%s: the slope limiter has no adjoint here", what);
+  return DG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -207,6 +214,7 @@ size_t dg_tape_size(const dg_ctx* c) { return c ? tape_doubles(c) : 0; }
 
 int dg_ssprk3_step_tape(dg_ctx* c, double* U, double dt, double* tape) {
   if (!c) return DG_EINVAL;
+  if (int rl = reject_limiter(c, "dg_ssprk3_step_tape")) return rl;
   if (!U || !tape) return fail(c, DG_EINVAL, "dg_ssprk3_step_tape: null pointer");
   int r = hipcheck(c, clear_tape_flags(c, tape, 1), "dg_ssprk3_step_tape");
   if (r) return r;
@@ -217,6 +225,7 @@ int dg_ssprk3_step_tape(dg_ctx* c, double* U, double dt, double* tape) {
 
 int dg_ssprk3_step_vjp_tape(dg_ctx* c, const double* tape, double dt, const double* lam_next, double* lam_n) {
   if (!c) return DG_EINVAL;
+  if (int rl = reject_limiter(c, "dg_ssprk3_step_vjp_tape")) return rl;
   if (!tape || !lam_next || !lam_n) return fail(c, DG_EINVAL, "dg_ssprk3_step_vjp_tape: null pointer");
   int r = ensure_adj(c);
   if (r) return r;
@@ -226,6 +235,7 @@ int dg_ssprk3_step_vjp_tape(dg_ctx* c, const double* tape, double dt, const doub
 
 int dg_ssprk3_run_tape(dg_ctx* c, double* U, double dt, int nsteps, double* tapes) {
   if (!c) return DG_EINVAL;
+  if (int rl = reject_limiter(c, "dg_ssprk3_run_tape")) return rl;
   if (!U || !tapes) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: null pointer");
   if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_tape: nsteps < 0");
   const size_t T = tape_doubles(c);
@@ -241,6 +251,7 @@ int dg_ssprk3_run_tape(dg_ctx* c, double* U, double dt, int nsteps, double* tape
 
 int dg_ssprk3_run_vjp_tape(dg_ctx* c, const double* tapes, double dt, int nsteps, double* lam) {
   if (!c) return DG_EINVAL;
+  if (int rl = reject_limiter(c, "dg_ssprk3_run_vjp_tape")) return rl;
   if (!tapes || !lam) return fail(c, DG_EINVAL, "dg_ssprk3_run_vjp_tape: null pointer");
   if (nsteps < 0) return fail(c, DG_EINVAL, "dg_ssprk3_run_vjp_tape: nsteps < 0");
   int r = ensure_adj(c);
@@ -256,6 +267,7 @@ int dg_ssprk3_run_vjp_tape(dg_ctx* c, const double* tapes, double dt, int nsteps
 
 int dg_ssprk3_step_vjp(dg_ctx* c, const double* Un, double dt, const double* lam_next, double* lam_n) {
   if (!c) return DG_EINVAL;
+  if (int rl = reject_limiter(c, "dg_ssprk3_step_vjp")) return rl;
   if (!Un || !lam_next || !lam_n) return fail(c, DG_EINVAL, "dg_ssprk3_step_vjp: null pointer");
   int r = ensure_adj(c);
   if (r) return r;

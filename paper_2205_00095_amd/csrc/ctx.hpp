@@ -6,6 +6,7 @@
 
 #include "../../include/dgsrhd.h"
 #include "launch.hpp"
+#include "launch_lim.hpp"
 
 namespace dgsrhd {
 // A validated mesh description and what is derived from it on the host.
@@ -16,6 +17,8 @@ struct MeshSetup {
   MeshArgs m{};
   int nv = 0, npe = 0;
   long long ntot = 0;
+  double xi[kMaxN1] = {};      // Gauss-Legendre nodes on [-1, 1]
+  double lim_inv_den = 0.0;    // 1 / sum_n w_n xi_{d,n}^2 of the slope limiter
 };
 }  // namespace dgsrhd
 
@@ -27,6 +30,7 @@ struct dg_ctx : dgsrhd::MeshSetup {
   double* U1 = nullptr;
   double* U2 = nullptr;
   double* adj = nullptr;     // adjoint scratch (allocated on first use)
+  double* avg = nullptr;     // element averages of the slope limiter (allocated with it)
   size_t adj_doubles = 0;
   dgsrhd::Counters* cnt = nullptr;
   dgsrhd::Counters last{};           // counter snapshot for sync-mode error reporting
@@ -48,4 +52,5 @@ hipError_t L_element(dg_ctx* c, int mode, const ElemArgs& a);
 hipError_t L_con2prim(dg_ctx* c, const double* U, double* W);
 hipError_t L_enforce(dg_ctx* c, double* U);
 hipError_t L_prim3(dg_ctx* c, const double* S, double* U);
+hipError_t L_limiter(dg_ctx* c, double* U, double* Wout);
 }  // namespace dgsrhd

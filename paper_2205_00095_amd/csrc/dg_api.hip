@@ -24,6 +24,7 @@ __global__ void k_reset_counters(Counters* cnt) {
     c->c2p_fail = c->c2p_noconv = c->trace_fallback = 0ull;
     c->flagged = c->smoothed = c->bad_average = c->bad_input = 0ull;
     c->first_bad = ~0ull;
+    c->limited = 0ull;
   }
 }
 
@@ -42,6 +43,7 @@ static hipError_t read_counters(const Counters* dev, Counters& out) {
     out.smoothed += h[i].smoothed;
     out.bad_average += h[i].bad_average;
     out.bad_input += h[i].bad_input;
+    out.limited += h[i].limited;
     out.first_bad = h[i].first_bad < out.first_bad ? h[i].first_bad : out.first_bad;
   }
   return hipSuccess;
@@ -56,6 +58,7 @@ static void to_diag(const Counters& h, dg_diag* out) {
   out->bad_average = (long long)h.bad_average;
   out->bad_input = (long long)h.bad_input;
   out->first_bad_elem = (h.first_bad == ~0ull) ? -1 : (long long)h.first_bad;
+  out->limited = (long long)h.limited;
 }
 
 }  // namespace dgsrhd
@@ -84,7 +87,7 @@ int hipcheck(dg_ctx* c, hipError_t e, const char* what) {
 // Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n, and the
 // Lagrange tables through barycentric weights.  Fixed-size arrays (p <= 3): no
 // allocation, so the allocation-free entry point can build its tables per call.
-void gl_tables(int p, int dim, Tables& t) {
+void gl_tables(int p, int dim, Tables& t, double* xout) {
   const int n = p + 1;
   double x[kMaxN1], w[kMaxN1];
   if (n == 1) {
@@ -136,6 +139,7 @@ void gl_tables(int p, int dim, Tables& t) {
     Dm[i][i] = diag;
   }
   std::memset(&t, 0, sizeof(t));
+  for (int i = 0; i < kMaxN1; ++i) xout[i] = i < n ? x[i] : 0.0;
   double wsum = 0.0;
   for (int i = 0; i < n; ++i) {
     double lp = 1.0, lm = 1.0;
@@ -196,6 +200,8 @@ const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s) {
   if (d.flux != DG_FLUX_HLL && d.flux != DG_FLUX_HLLC) return "flux must be HLL or HLLC";
   if (!(d.phys_eps > 0.0)) d.phys_eps = 1e-12;
   if (d.c2p_iters < 0 || d.c2p_iters > 1000) return "c2p_iters must be in 0..1000";
+  if (d.limiter != DG_LIMITER_NONE && d.limiter != DG_LIMITER_MINMOD) return "limiter must be none or minmod";
+  if (d.p == 0) d.limiter = DG_LIMITER_NONE;
   const long long nelem = (long long)d.n_elem[0] * d.n_elem[1] * d.n_elem[2];
   if (nelem > (1ll << 30)) return "mesh too large";
   s.nv = d.dim + 2;
@@ -214,7 +220,20 @@ const char* setup_mesh(const dg_mesh_desc* in, MeshSetup& s) {
   q.eps = d.phys_eps;
   q.c2p = d.c2p;
   q.c2p_iters = d.c2p_iters;
-  gl_tables(d.p, d.dim, s.t);
+  gl_tables(d.p, d.dim, s.t, s.xi);
+  {
+    // sum over the element's nodes of w_n xi_{d,n}^2: one line's sum times the others' weights
+    double den = 0.0, w1 = 0.0;
+    double x[kMaxN1];
+    for (int i = 0; i <= d.p; ++i) x[i] = 0.5 * (s.xi[i] - s.xi[d.p - i]);  // exact mirror symmetry
+    for (int i = 0; i <= d.p; ++i) s.xi[i] = x[i];
+    for (int i = 0; i <= d.p; ++i) {
+      den += s.t.w[i] * s.xi[i] * s.xi[i];
+      w1 += s.t.w[i];
+    }
+    for (int k = 1; k < d.dim; ++k) den *= w1;
+    s.lim_inv_den = den > 0.0 ? 1.0 / den : 0.0;
+  }
   MeshArgs& m = s.m;
   m.nex = d.n_elem[0];
   m.ney = d.n_elem[1];
@@ -298,6 +317,25 @@ hipError_t L_prim3(dg_ctx* c, const double* S, double* U) {
   return launch_prim3_to_cons_dim3(eos, S, U, c->ntot, c->q, c->cnt, c->stream);
 }
 
+// Element averages, then limiter + operator + recovery (Wout null: no recovery).
+hipError_t L_limiter(dg_ctx* c, double* U, double* Wout) {
+  LimArgs a{};
+  a.U = U;
+  a.avg = c->avg;
+  a.Wout = Wout;
+  for (int i = 0; i < kMaxN1; ++i) a.xi[i] = c->xi[i];
+  a.inv_den = c->lim_inv_den;
+  a.phys = c->desc.phys;
+  a.m = c->m;
+  a.t = c->t;
+  a.q = c->q;
+  a.cnt = c->cnt;
+  const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos;
+  if (dim == 1) return launch_limiter_dim1(p, eos, a, c->avg, c->stream);
+  if (dim == 2) return launch_limiter_dim2(p, eos, a, c->avg, c->stream);
+  return launch_limiter_dim3(p, eos, a, c->avg, c->stream);
+}
+
 ElemArgs base_args(dg_ctx* c) {
   ElemArgs a{};
   a.m = c->m;
@@ -355,6 +393,8 @@ int dg_init_mesh(const dg_mesh_desc* desc, void* hip_stream, dg_ctx** out) {
   if (e == hipSuccess) e = hipMalloc((void**)&c->U1, bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->U2, bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->cnt, sizeof(Counters) * kCounterSlots);
+  if (e == hipSuccess && c->desc.limiter)
+    e = hipMalloc((void**)&c->avg, sizeof(double) * (size_t)c->nv * (size_t)c->m.nelem);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->handoff, hipEventDisableTiming);
   if (e != hipSuccess) {
     std::fprintf(stderr, "dg_init_mesh: allocation failed: %s\n", hipGetErrorString(e));
@@ -451,6 +491,10 @@ int dg_enforce_physical(dg_ctx* c, double* U) {
 // Z = ca U^n + cb U^(k) (with the last stage's weights) in place of U^(k), whose
 // primitives it still writes, and the last stage forms Z + cb dt L(U^(k)) reading
 // only Z, one state read fewer per step.
+// With the slope limiter a stage is U^(k+1) = Pi(Lim(ca U^n + cb (U^(k) + dt L))):
+// the stage launch writes the unlimited combination (no operator, no recovery, no
+// folding, since Lim needs the neighbours' averages of the finished stage), then
+// the averages and the limiter launches finish it.
 static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, const char* what) {
   if (!c) return DG_EINVAL;
   if (!U) return fail(c, DG_EINVAL, "%s: null pointer", what);
@@ -469,7 +513,13 @@ static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, c
   const Stage tab3[3] = {{0.0, 1.0, 1.0, 0.0, 0.0, U, c->U1},
                          {0.75, 0.25, 1.0, 1.0 / 3.0, 2.0 / 3.0, c->U1, c->U2},
                          {0.0, 1.0, 2.0 / 3.0, 0.0, 0.0, c->U2, U}};
-  const Stage* tab = order == 1 ? tab1 : (order == 2 ? tab2 : tab3);
+  // the Shu-Osher weights as they stand (limiter)
+  const Stage lim2[2] = {{0.0, 1.0, 1.0, 0.0, 0.0, U, c->U1}, {0.5, 0.5, 1.0, 0.0, 0.0, c->U1, U}};
+  const Stage lim3[3] = {{0.0, 1.0, 1.0, 0.0, 0.0, U, c->U1},
+                         {0.75, 0.25, 1.0, 0.0, 0.0, c->U1, c->U2},
+                         {1.0 / 3.0, 2.0 / 3.0, 1.0, 0.0, 0.0, c->U2, U}};
+  const bool lim = c->desc.limiter != DG_LIMITER_NONE;
+  const Stage* tab = order == 1 ? tab1 : (order == 2 ? (lim ? lim2 : tab2) : (lim ? lim3 : tab3));
   double* Wa = c->Wa;
   double* Wb = c->Wb;
   int r = hipcheck(c, L_con2prim(c, U, Wa), what);
@@ -487,8 +537,15 @@ static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, c
       a.zb = tab[k].zb;
       a.out = tab[k].out;
       const bool last = (s == nsteps - 1) && (k == order - 1);
-      a.Wout = last ? nullptr : Wb;
-      if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+      if (lim) {
+        a.phys = 0;
+        a.Wout = nullptr;
+        if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+        if ((r = hipcheck(c, L_limiter(c, tab[k].out, last ? nullptr : Wb), what))) return r;
+      } else {
+        a.Wout = last ? nullptr : Wb;
+        if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+      }
       double* tmp = Wa; Wa = Wb; Wb = tmp;
     }
   }
@@ -541,6 +598,7 @@ void dg_destroy(dg_ctx* c) {
   (void)hipFree(c->U1);
   (void)hipFree(c->U2);
   (void)hipFree(c->adj);
+  (void)hipFree(c->avg);
   (void)hipFree(c->cnt);
   if (c->handoff) (void)hipEventDestroy(c->handoff);
   delete c;

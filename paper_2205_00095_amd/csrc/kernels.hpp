@@ -53,15 +53,17 @@ struct MeshArgs {
   double bw[3][2][5];           // fixed exterior primitives (rho, u_x, u_y, u_z, P) per d and end
 };
 
-// Event counters, one 64-byte set per slot.  A workgroup counts into slot
-// blockIdx.x mod kCounterSlots: device-scope atomics from every XCD on one cache
-// line serialise (on failure-heavy data that cost milliseconds per stage); the
+// Event counters, one 128-byte set (an L2 cache line) per slot.  A workgroup counts
+// into slot blockIdx.x mod kCounterSlots: device-scope atomics from every XCD on one
+// cache line serialise (on failure-heavy data that cost milliseconds per stage); the
 // host sums the slots (minimum for first_bad) when it reads them.
 struct Counters {
   unsigned long long c2p_fail, c2p_noconv, trace_fallback, flagged, smoothed, bad_average, bad_input;
   unsigned long long first_bad;  // lowest failing element (ULLONG_MAX if none)
+  unsigned long long limited;    // (element, component) pairs replaced by the slope limiter
+  unsigned long long pad[7];
 };
-static_assert(sizeof(Counters) == 64, "one cache line per slot");
+static_assert(sizeof(Counters) == 128, "one cache line per slot");
 constexpr int kCounterSlots = 256;
 
 __device__ __forceinline__ Counters* counter_slot(Counters* base) {

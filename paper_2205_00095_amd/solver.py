@@ -34,6 +34,7 @@ def _desc_from_config(cfg: dict, sync: bool) -> _lib.MeshDesc:
     for k, t in enumerate(cfg.get("bc_hi", (0, 0, 0))):
         d.bc_hi[k] = int(t)
     d.c2p_iters = int(cfg.get("c2p_iters", 0))
+    d.limiter = int(cfg.get("limiter", 0))
     for (k, end), state in cfg.get("bc_state", {}).items():
         for i in range(5):
             d.bc_state[(k * 2 + end) * 5 + i] = float(state[i])

@@ -65,6 +65,7 @@ def _desc(**over):
     {"bc": (1, 0, 0), "bc_hi": (3, 0, 0)},                        # a Dirichlet end without its state
     {"precision": 2},                                             # matrix-core sweeps exist for 2D p = 3 only
     {"c2p_iters": -1},                                            # fixed iteration count out of range
+    {"limiter": 2},                                               # no such limiter (the last field)
 ])
 def test_invalid_descriptions_are_rejected_without_a_gpu(change):
     """Validation runs on the host before any device call; the checks read the fields the
