@@ -19,6 +19,8 @@ physicality operator on.  Extra results on the same JSON line:
                  20) relative to the forward run, 128x128 p=2 ideal-gas mesh;
   roofline       the stage kernel against HBM, from algorithmic bytes per
                  DOF-stage (read U^(k), read U^n in stages 2-3, write U^(k+1)).
+  limiter        the cylindrical blast (512x512 p=2) with the slope limiter on
+                 and off: time per step, fraction of elements limited.
   paper_sweep    the paper's KH performance grid: HLL and HLLC, p = 0, 1, 2 with
                  RK1, SSPRK2, SSPRK3 on 256x512 .. 1024x2048 meshes (ideal EOS).
   cpu_baseline   the FP64 CPU oracle on the host cores for a bounded sample.
@@ -449,6 +451,44 @@ def random3d_leg(repeats=5):
                               "nonfinite_nodes after the step"}
 
 
+def limiter_leg(steps=20, warmup=2):
+    """The slope limiter at scale: the cylindrical blast (512x512 p=2, HLLC, SSP-RK3), the
+    same steps from the same initial state with the limiter on and off.  With it each
+    stage is three launches (the stage kernel without operator and recovery, element
+    averages, then limiter + operator + recovery); without it one fused launch."""
+    import torch
+    from paper_2205_00095_amd import workloads as wl
+    from paper_2205_00095_amd.solver import Solver
+    out = {}
+    for lim in (1, 0):
+        cfg = wl.make_config("blast2d", limiter=lim)
+        solver = Solver(cfg)
+        rho, v, P = wl.initial_primitives(cfg)
+        U0 = solver.set_state(torch.from_numpy(wl.pack_primitives(rho, v, P)).cuda())
+        U = U0.clone()
+        solver.run(U, cfg["dt"], warmup)
+        U.copy_(U0)
+        solver.reset_diagnostics()
+        seconds = _time_run(solver, U, cfg["dt"], steps, 0)
+        d = solver.diagnostics()
+        dofs = wl.n_dof(cfg)
+        nel = dofs // (cfg["p"] + 1) ** cfg["dim"]
+        out["on" if lim else "off"] = {
+            "ms_per_step": seconds / steps * 1e3, "dof_stage_per_s": dofs * steps * 3 / seconds,
+            "limited_per_element_stage": d["limited"] / (nel * steps * 3),
+            "smoothed_per_element_stage": d["smoothed"] / (nel * steps * 3),
+            "c2p_fail": d["c2p_fail"], "bad_average": d["bad_average"]}
+        solver.close()
+        del U, U0
+    nvar = 4
+    out["workload"] = "blast2d: 2D 512x512 elements p=2 ideal Gamma=5/3, HLLC, SSP-RK3, pressure ratio 1000"
+    out["limiter_overhead"] = out["on"]["ms_per_step"] / out["off"]["ms_per_step"] - 1.0
+    out["algorithmic_bytes_per_dof"] = {
+        "k_avg": nvar * 8.0, "k_limit": 3 * nvar * 8.0,
+        "note": "k_avg reads U; k_limit reads U and writes U and W (the last stage of a step writes no W)"}
+    return out
+
+
 def wave1d_leg(steps=100):
     """The 1D density wave (64 elements, p=2, ideal EOS): 100 SSP-RK3 steps at the fixed
     step 0.1/(2p+1) dx/c; the L1 error of D against the exact translated solution, the
@@ -693,6 +733,8 @@ def main(argv=None):
                     help="only run the 3D stress-field leg (64^3 p=2) and print its JSON")
     ap.add_argument("--adjoint", action="store_true",
                     help="only run the adjoint cost measurement (128x128 p=2, 200 steps) and print its JSON")
+    ap.add_argument("--limiter", action="store_true",
+                    help="only run the slope-limiter leg (2D blast 512x512 p=2, limiter on and off)")
     ap.add_argument("--rhs", action="store_true",
                     help="only time dg_rhs on the workload (50 calls after one warm-up) and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -721,6 +763,9 @@ def main(argv=None):
         return 0
     if args.adjoint:
         print(json.dumps(adjoint_ratio()), flush=True)
+        return 0
+    if args.limiter:
+        print(json.dumps(limiter_leg()), flush=True)
         return 0
     if args.rhs:
         cfg, solver, U = _setup(args.workload)
@@ -808,6 +853,7 @@ def main(argv=None):
         extras["hbm_copy_GBs"] = _copy_bandwidth() / 1e9
         extras["paper_sweep"] = paper_sweep()
         extras["random3d"] = random3d_leg()
+        extras["limiter"] = limiter_leg()
         c1, c1_final = wave1d_leg(100)
         extras["wave1d"] = c1
         extras["adjoint"] = adjoint_ratio()

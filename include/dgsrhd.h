@@ -96,15 +96,19 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * range 0..1000 (DG_EINVAL outside).
  * limiter = DG_LIMITER_MINMOD (p >= 1; ignored at p = 0) applies the slope limiter the
  * paper pairs with the operator for its p >= 1 shock runs (Sec. 2.3 names the minmod
- * limiter of van Leer 1979) after every SSP-RK stage, before the operator: per
- * element and conserved component, the slope along each d (the coefficient of xi_d in
- * the element's Legendre expansion, from mirror pairs of nodes) is replaced by the
- * minmod of itself and half the differences of the neighbouring element averages
- * (periodic wrap; a non-periodic end takes the element's own average); where any
- * slope changed, the component becomes its average plus the limited linear part.
- * Averages are kept.  Each stage then runs as separate launches (stage, averages,
- * limiter with operator and recovery).  The taped stepping and step-adjoint
- * entry points reject it (DG_EINVAL); dg_rhs and dg_rhs_vjp do not involve it. */
+ * limiter of van Leer 1979 and the scaling limiter of Moe, Rossmanith & Seal 2015)
+ * after every SSP-RK stage, before the operator: per element, the slope of each
+ * conserved component along each d (the coefficient of xi_d in the element's Legendre
+ * expansion, from mirror pairs of nodes) is bounded by minmod with the differences to
+ * the neighbouring element averages (periodic wrap; a non-periodic end takes the
+ * element's own average); the least ratio of bounded to own slope over the pairs whose
+ * bound moves the slope by more than 1e-10 of the component's energy scale is one
+ * factor theta <= 1 by which every node's deviation from the element average is
+ * scaled.  Averages are kept, and a node stays on the segment to the average.  Each
+ * stage then runs as two launches (the stage, writing the unlimited combination and
+ * its element averages; the limiter with the operator and the recovery).  The taped
+ * stepping and step-adjoint entry points reject it (DG_EINVAL); dg_rhs and dg_rhs_vjp
+ * do not involve it. */
 typedef struct {
   int dim, p;
   int n_elem[3];

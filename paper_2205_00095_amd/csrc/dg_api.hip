@@ -317,7 +317,8 @@ hipError_t L_prim3(dg_ctx* c, const double* S, double* U) {
   return launch_prim3_to_cons_dim3(eos, S, U, c->ntot, c->q, c->cnt, c->stream);
 }
 
-// Element averages, then limiter + operator + recovery (Wout null: no recovery).
+// Limiter + operator + recovery (Wout null: no recovery) on U, whose element averages
+// the stage launch wrote into c->avg.
 hipError_t L_limiter(dg_ctx* c, double* U, double* Wout) {
   LimArgs a{};
   a.U = U;
@@ -331,9 +332,9 @@ hipError_t L_limiter(dg_ctx* c, double* U, double* Wout) {
   a.q = c->q;
   a.cnt = c->cnt;
   const int dim = c->desc.dim, p = c->desc.p, eos = c->desc.eos;
-  if (dim == 1) return launch_limiter_dim1(p, eos, a, c->avg, c->stream);
-  if (dim == 2) return launch_limiter_dim2(p, eos, a, c->avg, c->stream);
-  return launch_limiter_dim3(p, eos, a, c->avg, c->stream);
+  if (dim == 1) return launch_limiter_dim1(p, eos, a, c->stream);
+  if (dim == 2) return launch_limiter_dim2(p, eos, a, c->stream);
+  return launch_limiter_dim3(p, eos, a, c->stream);
 }
 
 ElemArgs base_args(dg_ctx* c) {
@@ -492,9 +493,9 @@ int dg_enforce_physical(dg_ctx* c, double* U) {
 // primitives it still writes, and the last stage forms Z + cb dt L(U^(k)) reading
 // only Z, one state read fewer per step.
 // With the slope limiter a stage is U^(k+1) = Pi(Lim(ca U^n + cb (U^(k) + dt L))):
-// the stage launch writes the unlimited combination (no operator, no recovery, no
-// folding, since Lim needs the neighbours' averages of the finished stage), then
-// the averages and the limiter launches finish it.
+// the stage launch writes the unlimited combination and its element averages (no
+// operator, no recovery, no folding, since Lim needs the neighbours' averages of the
+// finished stage), then the limiter launch finishes it.
 static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, const char* what) {
   if (!c) return DG_EINVAL;
   if (!U) return fail(c, DG_EINVAL, "%s: null pointer", what);
@@ -540,7 +541,8 @@ static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, c
       if (lim) {
         a.phys = 0;
         a.Wout = nullptr;
-        if ((r = hipcheck(c, L_element(c, MODE_STAGE, a), what))) return r;
+        a.avg = c->avg;
+        if ((r = hipcheck(c, L_element(c, MODE_STAGE_LIM, a), what))) return r;
         if ((r = hipcheck(c, L_limiter(c, tab[k].out, last ? nullptr : Wb), what))) return r;
       } else {
         a.Wout = last ? nullptr : Wb;

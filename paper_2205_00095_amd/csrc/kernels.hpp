@@ -77,6 +77,7 @@ struct ElemArgs {
   double* out;        // R (rhs mode) or U^(k+1) (stage mode)
   double* Wout;       // primitives of U^(k+1), or null
   double* Pout;       // U^(k+1) before the physicality operator (adjoint tape), or null
+  double* avg;        // [NV][nelem] element averages of U^(k+1) (MODE_STAGE_LIM)
   double ca, cb, dt;  // U^(k+1) = ca U^n + cb (U^(k) + dt R); U^n is not read when ca = za = 0
   double za, zb;      // with za != 0 the stored output is za U^n + zb U^(k+1) (after the operator)
   int phys;
@@ -362,7 +363,9 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
 // MODE_RHS_FUSED reads U and recovers its own nodes and the halo elements across the
 // tile's boundary faces itself (one launch, no primitive buffer); MODE_STAGE is one
 // SSP-RK stage.
-enum { MODE_RHS = 0, MODE_STAGE = 1, MODE_RHS_FUSED = 2 };
+// MODE_STAGE_LIM is the stage ahead of the slope limiter: the RK combination only (no
+// operator, no recovery, no folding), and the element averages of the result.
+enum { MODE_RHS = 0, MODE_STAGE = 1, MODE_RHS_FUSED = 2, MODE_STAGE_LIM = 3 };
 // PREC_FP32: the volume and lift contractions in FP32 on the vector ALUs; PREC_FP32_MFMA:
 // the same with the volume sweeps on the matrix cores (2D, p = 3 only)
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32_MFMA = 2 };
@@ -699,6 +702,7 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   __shared__ double sFh[NV * FPB];
   __shared__ double sFref[(PREC != PREC_FP64) ? DIM * NV * EPB * NFP : 1];
   static_assert(PREC != PREC_FP32_MFMA || (DIM == 2 && P == 3), "MFMA sweeps are built for 2D p = 3");
+  constexpr bool kStage = MODE == MODE_STAGE || MODE == MODE_STAGE_LIM;
   __shared__ int sflag[(MODE == MODE_STAGE) ? NT : 1];
   __shared__ int svote[(NT + 63) / 64];
   // fused right-hand side: the primitives of the halo elements, recovered in the tile
@@ -909,8 +913,8 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
   }
   // the epilogue's state loads, issued before the barrier (inactive lanes read element 0)
   double Ukv[NV], U0v[NV];
-  const bool need_u0 = MODE == MODE_STAGE && (a.ca != 0.0 || a.za != 0.0);
-  if constexpr (MODE == MODE_STAGE) {
+  const bool need_u0 = kStage && (a.ca != 0.0 || a.za != 0.0);
+  if constexpr (kStage) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Ukv[v] = a.Uk[v * ntot + g];
 #pragma unroll
@@ -970,6 +974,28 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     for (int v = 0; v < NV; ++v) {
       const double uk = act ? Ukv[v] : 1.0;
       Un[v] = a.ca * U0[v] + a.cb * (uk + a.dt * R[v]);
+    }
+    if constexpr (MODE == MODE_STAGE_LIM) {
+      // the unlimited stage and its element averages (quadrature sum in node order);
+      // sF was last read in the volume phase, before the face phase's closing barrier
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.out[v * ntot + g] = Un[v];
+      }
+      double wn = t.w[node_coord<N1>(node, 0)];
+      if (DIM > 1) wn *= t.w[node_coord<N1>(node, 1)];
+      if (DIM > 2) wn *= t.w[node_coord<N1>(node, 2)];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sF[v * NTP + ln] = wn * Un[v];
+      __syncthreads();
+      if (act) {
+        for (int v = node; v < NV; v += NPE) {
+          double acc = 0.0;
+          for (int n = 0; n < NPE; ++n) acc += sF[v * NTP + el * ES + n];
+          a.avg[(long long)v * m.nelem + e] = acc * t.inv_wsum;
+        }
+      }
+      return;
     }
     if (a.Pout && act) {
 #pragma unroll

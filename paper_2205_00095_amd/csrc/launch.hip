@@ -32,6 +32,10 @@ hipError_t by_mode(int mode, int flux, const ElemArgs& a, hipStream_t s) {
     if constexpr (TileGeo<DIM, P>::kFusedRhs) return by_flux<DIM, P, EOS, PREC, MODE_RHS_FUSED>(flux, a, s);
     return hipErrorInvalidValue;
   }
+  if (mode == MODE_STAGE_LIM) {
+    if constexpr (P > 0) return by_flux<DIM, P, EOS, PREC, MODE_STAGE_LIM>(flux, a, s);
+    return hipErrorInvalidValue;
+  }
   return mode == MODE_RHS ? by_flux<DIM, P, EOS, PREC, MODE_RHS>(flux, a, s)
                           : by_flux<DIM, P, EOS, PREC, MODE_STAGE>(flux, a, s);
 }

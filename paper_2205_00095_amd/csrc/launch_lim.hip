@@ -1,4 +1,4 @@
-// Template instantiation and launch of the slope-limiter kernels for one spatial
+// Template instantiation and launch of the slope-limiter kernel for one spatial
 // dimension (compiled once per dimension with -DDG_DIM=1, 2 or 3).
 #include "launch_lim.hpp"
 
@@ -11,12 +11,9 @@ namespace dgsrhd {
 namespace {
 
 template <int DIM, int P>
-hipError_t run_limiter(int eos, const LimArgs& a, double* avg, hipStream_t s) {
+hipError_t run_limiter(int eos, const LimArgs& a, hipStream_t s) {
   using G = Geo<DIM, P>;
   const int nb = (a.m.nelem + G::EPB - 1) / G::EPB;
-  hipLaunchKernelGGL((k_avg<DIM, P>), dim3(nb), dim3(G::NT), 0, s, a.U, avg, a.m, a.t);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (eos == EOS_IDEAL)
     hipLaunchKernelGGL((k_limit<DIM, P, EOS_IDEAL>), dim3(nb), dim3(G::NT), 0, s, a);
   else
@@ -29,11 +26,11 @@ hipError_t run_limiter(int eos, const LimArgs& a, double* avg, hipStream_t s) {
 #define DG_CAT2(a, b) a##b
 #define DG_CAT(a, b) DG_CAT2(a, b)
 
-hipError_t DG_CAT(launch_limiter_dim, DG_DIM)(int p, int eos, const LimArgs& a, double* avg, hipStream_t s) {
+hipError_t DG_CAT(launch_limiter_dim, DG_DIM)(int p, int eos, const LimArgs& a, hipStream_t s) {
   switch (p) {
-    case 1: return run_limiter<DG_DIM, 1>(eos, a, avg, s);
-    case 2: return run_limiter<DG_DIM, 2>(eos, a, avg, s);
-    case 3: return run_limiter<DG_DIM, 3>(eos, a, avg, s);
+    case 1: return run_limiter<DG_DIM, 1>(eos, a, s);
+    case 2: return run_limiter<DG_DIM, 2>(eos, a, s);
+    case 3: return run_limiter<DG_DIM, 3>(eos, a, s);
     default: return hipErrorInvalidValue;
   }
 }

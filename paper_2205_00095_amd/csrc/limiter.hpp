@@ -2,8 +2,8 @@
 // 1979 and the scaling limiter of Moe, Rossmanith & Seal 2015 for the p >= 1 shock
 // runs): minmod-bounded slopes applied as one scaling factor per element.
 //
-// k_avg     element averages of every component, [var][element], one element per
-//           group of NPE lanes (the quadrature sum in node order).
+// The stage launch ahead of it (k_element in MODE_STAGE_LIM) writes the unlimited
+// stage and its element averages, [var][element].
 // k_limit   per element: for each component k and direction d the slope s, the
 //           coefficient of xi_d in the element's Legendre expansion (sum_n w_n
 //           xi_{d,n} u_n / sum_n w_n xi_{d,n}^2, mirror nodes paired so that a constant
@@ -17,8 +17,9 @@
 //           primitives, all before one write of U and W.  One factor for all
 //           components keeps every node on the segment to the (admissible) average.
 //
-// Both kernels use the workgroup layout of the operator kernel: EPB consecutive
-// elements per workgroup, one node per lane.
+// Workgroup layout of the operator kernel: EPB consecutive elements, one node per
+// lane; the (direction, component) pairs of an element are spread over its lanes,
+// whose average loads are issued before the first barrier.
 #pragma once
 #include "kernels.hpp"
 
@@ -26,7 +27,7 @@ namespace dgsrhd {
 
 struct LimArgs {
   double* U;             // stage output, limited in place
-  const double* avg;     // [NV][nelem] averages of U (k_avg)
+  const double* avg;     // [NV][nelem] averages of U (written by the stage launch)
   double* Wout;          // primitives of the limited state, or null
   double xi[kMaxN1];     // reference nodes on [-1, 1]
   double inv_den;        // 1 / sum_n w_n xi_{d,n}^2 (the same for every d)
@@ -46,29 +47,6 @@ __device__ __forceinline__ double node_weight(const Tables& t, int node) {
   return wn;
 }
 
-template <int DIM, int P>
-__global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_avg(const double* __restrict__ U, double* __restrict__ avg,
-                                                         MeshArgs m, Tables t) {
-  using G = Geo<DIM, P>;
-  constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, EPB = G::EPB;
-  __shared__ double sbuf[NV * NT];
-  const int tid = threadIdx.x;
-  const int el = tid / NPE, node = tid % NPE;
-  const long long e = (long long)blockIdx.x * EPB + el;
-  const bool act = e < m.nelem;
-  const long long g = e * NPE + node;
-  const double wn = node_weight<DIM, P>(t, node);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) sbuf[v * NT + tid] = act ? wn * U[v * m.ntot + g] : 0.0;
-  __syncthreads();
-  if (!act) return;
-  for (int v = node; v < NV; v += NPE) {
-    double acc = 0.0;
-    for (int n = 0; n < NPE; ++n) acc += sbuf[v * NT + el * NPE + n];
-    avg[(long long)v * m.nelem + e] = acc * t.inv_wsum;
-  }
-}
-
 __device__ __forceinline__ double minmod3(double a, double b, double c) {
   const bool same = (a > 0.0 && b > 0.0 && c > 0.0) || (a < 0.0 && b < 0.0 && c < 0.0);
   const double mag = fmin(fmin(fabs(a), fabs(b)), fabs(c));
@@ -85,13 +63,24 @@ __device__ __forceinline__ int mirror_node(int node, int d) {
 
 constexpr double kLimEps = 1e-10;
 
+// neighbour of element (x, y, z) along d on side dir, or the element itself at a
+// non-periodic end
+__device__ __forceinline__ int neighbour_or_self(const MeshArgs& m, const int* c, int e, int d, int dir) {
+  const int n = d == 0 ? m.nex : (d == 1 ? m.ney : m.nez);
+  const int stride = d == 0 ? 1 : (d == 1 ? m.nex : m.nex * m.ney);
+  const int k = c[d] + dir;
+  if (k < 0) return m.periodic[d] ? e + (n - 1) * stride : e;
+  if (k >= n) return m.periodic[d] ? e - (n - 1) * stride : e;
+  return e + dir * stride;
+}
+
 template <int DIM, int P, int EOS>
 __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
   using G = Geo<DIM, P>;
   constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, EPB = G::EPB, N1 = G::N1;
-  constexpr int NS = DIM * NV;  // (direction, component) pairs per element
+  constexpr int NS = DIM * NV;               // (direction, component) pairs per element
+  constexpr int KP = (NS + NPE - 1) / NPE;   // pairs per lane
   __shared__ double sbuf[NV * NT];
-  __shared__ double sterm[NS * NT];
   __shared__ double sratio[EPB * NS];
   __shared__ int sflag[NT];
   __shared__ int svote[(NT + 63) / 64];
@@ -101,53 +90,66 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
   const long long e = (long long)blockIdx.x * EPB + el;
   const bool act = e < m.nelem;
   const long long g = e * NPE + node;
+  const long long ne = m.nelem;
   double u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    u[v] = act ? a.U[v * m.ntot + g] : 1.0;
-    sbuf[v * NT + tid] = u[v];
-  }
-  __syncthreads();
-  // odd part of each mirror pair times w_n xi_{d,n}
-  const double wn = node_weight<DIM, P>(a.t, node);
+  for (int v = 0; v < NV; ++v) u[v] = act ? a.U[v * m.ntot + g] : 1.0;
+  // this lane's pairs: own and neighbour averages, and the element's energy scale
+  double ub[KP], up[KP], um[KP];
+  double E = 0.0;
+  if (act) {
+    const int ie = (int)e;
+    const int c[3] = {ie % m.nex, (ie / m.nex) % m.ney, ie / (m.nex * m.ney)};
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const int mn = el * NPE + mirror_node<DIM, N1>(node, d);
-    const double wx = wn * a.xi[node_coord<N1>(node, d)];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sterm[(d * NV + v) * NT + tid] = wx * (0.5 * (u[v] - sbuf[v * NT + mn]));
-  }
-  __syncthreads();
-  // one lane per (d, v) pair: slope, minmod bound, ratio
-  for (int k = node; k < NS; k += NPE) {
-    double ratio = 1.0;
-    if (act) {
-      const int d = k / NV, v = k % NV;
-      double acc = 0.0;
-      for (int n = 0; n < NPE; ++n) acc += sterm[k * NT + el * NPE + n];
-      const double s = acc * a.inv_den;
-      const double* av = a.avg + (long long)v * m.nelem;
-      const double ub = av[e];
-      const int ep = neighbour(m, (int)e, d, +1), em = neighbour(m, (int)e, d, -1);
-      const double fwd = (ep < 0 ? ub : av[ep]) - ub;
-      const double bwd = ub - (em < 0 ? ub : av[em]);
-      const double sl = minmod3(s, fwd, bwd);
-      const double E = fabs(a.avg[(long long)(NV - 1) * m.nelem + e] + a.avg[e] * a.q.c2);
-      const double sig = v == 0 ? E * a.q.inv_c2 : (v == NV - 1 ? E : E * a.q.inv_c);
-      if (fabs(s - sl) > kLimEps * sig) ratio = sl / s;
+    for (int j = 0; j < KP; ++j) {
+      const int k = node + j * NPE;
+      ub[j] = up[j] = um[j] = 0.0;
+      if (k < NS) {
+        const int d = k / NV, v = k % NV;
+        const double* av = a.avg + v * ne;
+        ub[j] = av[e];
+        up[j] = av[neighbour_or_self(m, c, ie, d, +1)];
+        um[j] = av[neighbour_or_self(m, c, ie, d, -1)];
+      }
     }
-    sratio[el * NS + k] = ratio;
+    if (node < NS) E = fabs(a.avg[(NV - 1) * ne + e] + a.avg[e] * a.q.c2);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sbuf[v * NT + tid] = u[v];
+  __syncthreads();
+  // slope of each pair from the odd parts of the mirror pairs of nodes, minmod bound, ratio
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const int k = node + j * NPE;
+    if (k < NS) {
+      double ratio = 1.0;
+      if (act) {
+        const int d = k / NV, v = k % NV;
+        const double* row = sbuf + v * NT + el * NPE;
+        double acc = 0.0;
+        for (int n = 0; n < NPE; ++n) {
+          const double wx = node_weight<DIM, P>(a.t, n) * a.xi[node_coord<N1>(n, d)];
+          acc += wx * (0.5 * (row[n] - row[mirror_node<DIM, N1>(n, d)]));
+        }
+        const double s = acc * a.inv_den;
+        const double sl = minmod3(s, up[j] - ub[j], ub[j] - um[j]);
+        const double sig = v == 0 ? E * a.q.inv_c2 : (v == NV - 1 ? E : E * a.q.inv_c);
+        if (fabs(s - sl) > kLimEps * sig) ratio = sl / s;
+      }
+      sratio[el * NS + k] = ratio;
+    }
   }
   __syncthreads();
   double th = 1.0;
+#pragma unroll
   for (int k = 0; k < NS; ++k) th = fmin(th, sratio[el * NS + k]);
   const bool lim = act && th < 1.0;
   count_wave(&counter_slot(a.cnt)->limited, lim && node == 0);
   if (lim) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double ub = a.avg[(long long)v * m.nelem + e];
-      u[v] = ub + th * (u[v] - ub);
+      const double avv = a.avg[v * ne + e];
+      u[v] = avv + th * (u[v] - avv);
     }
   }
   if (a.phys) physicality_block_t<DIM, P, NT>(u, act, tid, el, node, a.t, a.q, counter_slot(a.cnt), sbuf, sflag, svote);
@@ -155,6 +157,8 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) a.U[v * m.ntot + g] = u[v];
   if (a.Wout) {
+    // started as outside a stage: reading the stage input's primitives for a warm start
+    // cost more (one more state read) than the iterations it saved
     double w[NV];
     const int st = con2prim<EOS, DIM>(u, w, a.q);
     count_c2p(counter_slot(a.cnt), st, e);

@@ -24,6 +24,9 @@ Workloads (the paper's tests they stand in for are named per function):
 * ``random3d``  3D periodic cube of i.i.d. lognormal densities/pressures and
                 random-direction velocities with Lorentz factor up to 20, a
                 stress case for the physicality-enforcing operator.
+* ``blast2d``   cylindrical blast wave (pressure ratio 1000 across a circle), 2D,
+                outflow, slope limiter on: the shock workload at scale (the
+                paper's limited runs are its 1D Riemann problems).
 """
 from __future__ import annotations
 
@@ -62,6 +65,8 @@ def make_config(kind: str, **over) -> dict:
                       ideal Gamma=4/3: the linear-wave convergence test.
       ``random3d``    3D periodic 64^3 elements, p=2, ideal Gamma=4/3,
                       FP32 contractions, physicality operator on, 20 steps.
+      ``blast2d``     2D cylindrical blast, 512x512 elements, p=2, ideal
+                      Gamma=5/3, HLLC, slope limiter and operator on, 20 steps.
     Keyword overrides replace entries (e.g. ``n_elem=(8, 8, 1)``).
     """
     if kind == "wave1d":
@@ -94,6 +99,12 @@ def make_config(kind: str, **over) -> dict:
                    bc=(PERIODIC, PERIODIC, PERIODIC), eos=EOS_IDEAL, gamma_ad=4.0 / 3.0,
                    c=1.0, c2p=C2P_NEWTON, precision=FP32_CONTRACT, phys=True, steps=20,
                    init="random3d")
+    elif kind == "blast2d":
+        # p = 2 with SSP-RK3 and the slope limiter, as the paper's limited shock runs
+        cfg = dict(dim=2, p=2, n_elem=(512, 512, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                   bc=(OUTFLOW, OUTFLOW, OUTFLOW), eos=EOS_IDEAL, gamma_ad=5.0 / 3.0,
+                   c=1.0, c2p=C2P_NEWTON, precision=FP64, phys=True, steps=20, init="blast",
+                   flux=FLUX_HLLC, limiter=1)
     else:
         raise ValueError(f"unknown workload {kind!r}")
     cfg["kind"] = kind
@@ -303,6 +314,16 @@ def random3d_primitives(cfg: dict, seed: int = 5):
     return rho, v, P
 
 
+def blast_primitives(cfg: dict):
+    """At rest, density 1; pressure 100 within radius 0.2 of the domain's centre, 0.1
+    outside (a cylinder in 2D, a sphere in 3D)."""
+    X = node_coords(cfg)
+    r2 = sum((X[d] - 0.5 * (cfg["lo"][d] + cfg["hi"][d])) ** 2 for d in range(cfg["dim"]))
+    shape = field_shape(cfg)
+    P = np.where(r2 < 0.04, 100.0, 0.1)
+    return np.ones(shape), np.zeros((cfg["dim"],) + shape), P
+
+
 def initial_primitives(cfg: dict, seed: int | None = None):
     """Dispatch on cfg['init']; returns (rho, v, P) with v the 3-velocity."""
     init = cfg.get("init")
@@ -318,6 +339,8 @@ def initial_primitives(cfg: dict, seed: int | None = None):
         return sound_primitives(cfg)
     if init in ("entropy", "shear2", "shear3"):
         return zero_mode_primitives(cfg, init)
+    if init == "blast":
+        return blast_primitives(cfg)
     raise ValueError(f"unknown init {init!r}")
 
 
