@@ -454,7 +454,7 @@ def random3d_leg(repeats=5):
 def limiter_leg(steps=20, warmup=2):
     """The slope limiter at scale: the cylindrical blast (512x512 p=2, HLLC, SSP-RK3), the
     same steps from the same initial state with the limiter on and off.  With it each
-    stage is three launches (the stage kernel without operator and recovery, element
+    stage is two launches (the stage kernel writing the unlimited stage and its element
     averages, then limiter + operator + recovery); without it one fused launch."""
     import torch
     from paper_2205_00095_amd import workloads as wl
@@ -484,8 +484,10 @@ def limiter_leg(steps=20, warmup=2):
     out["workload"] = "blast2d: 2D 512x512 elements p=2 ideal Gamma=5/3, HLLC, SSP-RK3, pressure ratio 1000"
     out["limiter_overhead"] = out["on"]["ms_per_step"] / out["off"]["ms_per_step"] - 1.0
     out["algorithmic_bytes_per_dof"] = {
-        "k_avg": nvar * 8.0, "k_limit": 3 * nvar * 8.0,
-        "note": "k_avg reads U; k_limit reads U and writes U and W (the last stage of a step writes no W)"}
+        "stage": _stage_bytes_per_dof(nvar), "k_limit": 3 * nvar * 8.0,
+        "note": ("stage (k_element, MODE_STAGE_LIM): read U^(k), read U^n in stages 2-3, write U^(k+1) "
+                 "(mean over the three stages; the element averages it also writes are 1/9 of a state); "
+                 "k_limit: read U, write U and W (the last stage of a run writes no W)")}
     return out
 
 
