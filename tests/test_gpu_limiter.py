@@ -110,6 +110,8 @@ CASES = {
     # the benchmark's cylindrical blast at a size the oracle finishes in seconds
     "blast2d 24x24 p=2": (lambda: _workload("blast2d", n_elem=(24, 24, 1)), 3, 3,
                           AMPLIFIED_BARS["blast2d 24x24 p=2 limited step"]),
+    # the Taub-Matthews recovery inside the limiter kernel (1-ulp response 4e-14)
+    "blast2d TM 16x16 p=3": (lambda: _workload("blast2d", n_elem=(16, 16, 1), p=3, eos=wl.EOS_TM), 3, 3, None),
 }
 
 
@@ -155,6 +157,26 @@ def test_limited_steps_match_oracle(case, monkeypatch):
         total += stats.get("limited", 0)
         U = U_next
     assert total > 0  # the limiter acted in every case
+
+
+def test_fp32_form_with_the_limiter():
+    """The FP32-contraction form under the limiter (the limiter itself, the operator and
+    the recovery stay FP64): 20 steps of the 48x48 p=3 blast stay admissible and within
+    1e-5 (L1, relative) of the FP64 run."""
+    from paper_2205_00095_amd.solver import Solver
+    out = []
+    for prec in (wl.FP64, wl.FP32_CONTRACT):
+        cfg, prims = _workload("blast2d", n_elem=(48, 48, 1), p=3, precision=prec)
+        s = Solver(cfg)
+        U = s.set_state(torch.from_numpy(prims).cuda())
+        s.run(U, cfg["dt"], 20)
+        d = s.diagnostics()
+        print(f"precision {prec}: {d}", flush=True)
+        assert d["c2p_fail"] == 0 and d["bad_average"] == 0 and d["limited"] > 0
+        out.append(U.cpu())
+    rel = float((out[1] - out[0]).abs().sum() / out[0].abs().sum())
+    print(f"L1 relative difference FP32 form vs FP64: {rel:.2e}", flush=True)
+    assert rel <= 1e-5
 
 
 def test_order_zero_ignores_the_limiter():
