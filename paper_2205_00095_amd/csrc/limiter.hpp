@@ -87,7 +87,9 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
   const MeshArgs& m = a.m;
   const int tid = threadIdx.x;
   const int el = tid / NPE, node = tid % NPE;
-  const long long e = (long long)blockIdx.x * EPB + el;
+  // XCD-aware order: each XCD takes a contiguous range of element groups, so the rows
+  // of neighbour averages a group gathers are mostly in that XCD's L2 already
+  const long long e = (long long)xcd_tile(blockIdx.x, gridDim.x) * EPB + el;
   const bool act = e < m.nelem;
   const long long g = e * NPE + node;
   const long long ne = m.nelem;
