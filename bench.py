@@ -521,6 +521,25 @@ def wave1d_leg(steps=100):
            "dof_stage_per_s": dofs * steps * 3 / sec, "stage_us": sec / (3 * steps) * 1e6,
            "note": "launch-bound (192 DOF); L1 = sum over nodes of (dx/2) w_q |D_h - D_exact|"}
     final = U.cpu()
+    # the same 100 steps captured in a HIP graph and replayed (no host launches)
+    Ug = U0.clone()
+    graph = solver.graph_run(Ug, cfg["dt"], steps)
+    Ug.copy_(U0)
+    graph.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(Ug.cpu(), final))
+    reps = 5
+    Ug.copy_(U0)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gsec = e0.elapsed_time(e1) / 1e3 / reps
+    out["graph"] = {"dof_stage_per_s": dofs * steps * 3 / gsec, "stage_us": gsec / (3 * steps) * 1e6,
+                    "replay_equals_eager_run": same,
+                    "note": f"{steps} steps captured once (Solver.graph_run), {reps} replays timed"}
     solver.close()
     return out, final
 

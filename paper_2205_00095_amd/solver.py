@@ -136,6 +136,24 @@ class Solver:
                         "dg_ssprk_run")
         return U
 
+    def graph_run(self, U: torch.Tensor, dt: float, nsteps: int, order: int = 3):
+        """Capture `run(U, dt, nsteps, order)` into a HIP graph and return it (a
+        torch.cuda.CUDAGraph): each replay advances U by nsteps steps, launching the
+        library's kernels without the host (for launch-bound meshes).  The context's
+        stream is moved to the capture stream before the capture begins, so the graph
+        holds only the library's kernel launches.  Replays use the context's scratch
+        like any call: replays and other calls on this context must be ordered (one
+        stream, or the caller's events)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self._sync_stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.run(U, dt, nsteps, order)
+        torch.cuda.current_stream().wait_stream(s)
+        return g
+
     def rhs_vjp(self, U: torch.Tensor, lamR: torch.Tensor, out: torch.Tensor | None = None):
         lamU = self.empty() if out is None else out
         self._sync_stream()
