@@ -19,6 +19,9 @@ physicality operator on.  Extra results on the same JSON line:
                  20) relative to the forward run, 128x128 p=2 ideal-gas mesh;
   roofline       the stage kernel against HBM, from algorithmic bytes per
                  DOF-stage (read U^(k), read U^n in stages 2-3, write U^(k+1)).
+  shard_share    one GPU's block of the 512x512 p=3 mesh split over 8 GPUs
+                 (128x256 elements), FP64 and FP32 form, with the per-stage
+                 exchange volume of such a split.
   limiter        the cylindrical blast (512x512 p=2) with the slope limiter on
                  and off: time per step, fraction of elements limited.
   paper_sweep    the paper's KH performance grid: HLL and HLLC, p = 0, 1, 2 with
@@ -491,6 +494,32 @@ def limiter_leg(steps=20, warmup=2):
     return out
 
 
+def shard_leg(steps=50, warmup=5):
+    """One GPU's share of the 512x512 p=3 Taub-Matthews mesh split over 8 GPUs as 4x2
+    blocks: a 128x256-element block, timed as a whole mesh (its outer faces stand in for
+    the halo faces that an exchange would supply), in FP64 and in the FP32 form; with
+    the per-stage exchange volume such a split would move (the primitive traces of the
+    block's boundary faces) and its time on one xGMI link."""
+    from paper_2205_00095_amd import workloads as wl
+    out = {}
+    for name, prec in (("fp64", wl.FP64), ("fp32_contract", wl.FP32_CONTRACT)):
+        cfg, solver, U = _setup("kh_tm", n_elem=(128, 256, 1), precision=prec)
+        sec = _time_run(solver, U, cfg["dt"], steps, warmup)
+        dofs = wl.n_dof(cfg)
+        out[name] = {"stage_us": sec / (3 * steps) * 1e6, "dof_stage_per_s": dofs * steps * 3 / sec}
+        solver.close()
+        del U
+    nx, ny, n1, nv = 128, 256, 4, 4
+    faces = 2 * (nx + ny)            # boundary faces of the block (every side has a neighbour)
+    exch = faces * n1 * nv * 8.0     # bytes of primitive traces sent per stage
+    out.update({"block": "128x256 elements p=3 TM (512x512 over 4x2 GPUs)", "dof": nx * ny * n1 * n1,
+                "exchange_bytes_per_stage": exch,
+                "exchange_us_one_xgmi_link": exch / 153e9 * 1e6,
+                "note": "the block's boundary faces are periodic/outflow here; a split run would take "
+                        "them from the neighbours' traces, sent once per stage"})
+    return out
+
+
 def wave1d_leg(steps=100):
     """The 1D density wave (64 elements, p=2, ideal EOS): 100 SSP-RK3 steps at the fixed
     step 0.1/(2p+1) dx/c; the L1 error of D against the exact translated solution, the
@@ -805,6 +834,17 @@ def main(argv=None):
     dofs = wl.n_dof(cfg)
     nvar = cfg["dim"] + 2
     seconds = _time_run(solver, U, cfg["dt"], args.steps, args.warmup)
+    # the same number of steps captured in a HIP graph and replayed once (no host launches)
+    graph = solver.graph_run(U, cfg["dt"], args.steps)
+    stream = torch.cuda.current_stream()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    g0.record(stream)
+    graph.replay()
+    g1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms_per_step = g0.elapsed_time(g1) / args.steps
+    del graph
     t_c2p = _time_con2prim(solver, U)
     t_rhs = _time_rhs(solver, U)
     stage_s = max(seconds - t_c2p, 1e-12) / (3 * args.steps)
@@ -821,6 +861,7 @@ def main(argv=None):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": seconds / args.steps * 1e3,
+        "graph_ms_per_step": graph_ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -875,6 +916,7 @@ def main(argv=None):
         extras["paper_sweep"] = paper_sweep()
         extras["random3d"] = random3d_leg()
         extras["limiter"] = limiter_leg()
+        extras["shard_share"] = shard_leg()
         c1, c1_final = wave1d_leg(100)
         extras["wave1d"] = c1
         extras["adjoint"] = adjoint_ratio()
