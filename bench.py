@@ -487,10 +487,10 @@ def limiter_leg(steps=20, warmup=2):
     out["workload"] = "blast2d: 2D 512x512 elements p=2 ideal Gamma=5/3, HLLC, SSP-RK3, pressure ratio 1000"
     out["limiter_overhead"] = out["on"]["ms_per_step"] / out["off"]["ms_per_step"] - 1.0
     out["algorithmic_bytes_per_dof"] = {
-        "stage": _stage_bytes_per_dof(nvar), "k_limit": 3 * nvar * 8.0,
+        "stage": _stage_bytes_per_dof(nvar), "k_limit": nvar * 8.0,
         "note": ("stage (k_element, MODE_STAGE_LIM): read U^(k), read U^n in stages 2-3, write U^(k+1) "
-                 "(mean over the three stages; the element averages it also writes are 1/9 of a state); "
-                 "k_limit: read U, write U and W (the last stage of a run writes no W)")}
+                 "(mean over the three stages; it also writes the averages and the next stage's "
+                 "primitives); k_limit: read U, plus U and W rewritten at the nodes that changed")}
     return out
 
 

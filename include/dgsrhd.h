@@ -105,8 +105,9 @@ enum { DG_CONSERVED = 0, DG_PRIMITIVE = 1 };
  * bound moves the slope by more than 1e-10 of the component's energy scale is one
  * factor theta <= 1 by which every node's deviation from the element average is
  * scaled.  Averages are kept, and a node stays on the segment to the average.  Each
- * stage then runs as two launches (the stage, writing the unlimited combination and
- * its element averages; the limiter with the operator and the recovery).  The taped
+ * stage then runs as two launches (the stage, writing the unlimited combination, its
+ * element averages and its primitives; the limiter with the operator, rewriting U
+ * and the primitives of the nodes that changed).  The taped
  * stepping and step-adjoint entry points reject it (DG_EINVAL); dg_rhs and dg_rhs_vjp
  * do not involve it. */
 typedef struct {

@@ -493,9 +493,10 @@ int dg_enforce_physical(dg_ctx* c, double* U) {
 // primitives it still writes, and the last stage forms Z + cb dt L(U^(k)) reading
 // only Z, one state read fewer per step.
 // With the slope limiter a stage is U^(k+1) = Pi(Lim(ca U^n + cb (U^(k) + dt L))):
-// the stage launch writes the unlimited combination and its element averages (no
-// operator, no recovery, no folding, since Lim needs the neighbours' averages of the
-// finished stage), then the limiter launch finishes it.
+// the stage launch writes the unlimited combination, its element averages and its
+// primitives (no operator, no folding, since Lim needs the neighbours' averages of
+// the finished stage), then the limiter launch finishes it, rewriting U and W only
+// where it or the operator changed a node.
 static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, const char* what) {
   if (!c) return DG_EINVAL;
   if (!U) return fail(c, DG_EINVAL, "%s: null pointer", what);
@@ -540,7 +541,7 @@ static int ssprk_steps(dg_ctx* c, double* U, double dt, int nsteps, int order, c
       const bool last = (s == nsteps - 1) && (k == order - 1);
       if (lim) {
         a.phys = 0;
-        a.Wout = nullptr;
+        a.Wout = last ? nullptr : Wb;
         a.avg = c->avg;
         if ((r = hipcheck(c, L_element(c, MODE_STAGE_LIM, a), what))) return r;
         if ((r = hipcheck(c, L_limiter(c, tab[k].out, last ? nullptr : Wb), what))) return r;

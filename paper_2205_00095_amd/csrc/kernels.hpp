@@ -363,8 +363,8 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
 // MODE_RHS_FUSED reads U and recovers its own nodes and the halo elements across the
 // tile's boundary faces itself (one launch, no primitive buffer); MODE_STAGE is one
 // SSP-RK stage.
-// MODE_STAGE_LIM is the stage ahead of the slope limiter: the RK combination only (no
-// operator, no recovery, no folding), and the element averages of the result.
+// MODE_STAGE_LIM is the stage ahead of the slope limiter: the RK combination (no
+// operator, no folding), the element averages of the result and its primitives.
 enum { MODE_RHS = 0, MODE_STAGE = 1, MODE_RHS_FUSED = 2, MODE_STAGE_LIM = 3 };
 // PREC_FP32: the volume and lift contractions in FP32 on the vector ALUs; PREC_FP32_MFMA:
 // the same with the volume sweeps on the matrix cores (2D, p = 3 only)
@@ -994,6 +994,19 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
           for (int n = 0; n < NPE; ++n) acc += sF[v * NTP + el * ES + n];
           a.avg[(long long)v * m.nelem + e] = acc * t.inv_wsum;
         }
+      }
+      // the next stage's primitives of every node, Newton started from this stage's
+      // input (the limiter launch recovers again only the nodes it changes); not
+      // counted here: a node whose recovery fails is marked with a NaN density, and the
+      // limiter launch recovers and counts it
+      if (act && a.Wout) {
+        double Wn[NV], Wp[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Wp[v] = sW[v * NTP + ln];
+        const int st = con2prim<EOS, DIM>(Un, Wn, q, Wp, false);
+        if (st != C2P_OK) Wn[0] = __builtin_nan("");
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.Wout[v * ntot + g] = Wn[v];
       }
       return;
     }

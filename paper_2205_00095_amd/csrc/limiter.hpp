@@ -3,7 +3,7 @@
 // runs): minmod-bounded slopes applied as one scaling factor per element.
 //
 // The stage launch ahead of it (k_element in MODE_STAGE_LIM) writes the unlimited
-// stage and its element averages, [var][element].
+// stage, its element averages ([var][element]) and its primitives.
 // k_limit   per element: for each component k and direction d the slope s, the
 //           coefficient of xi_d in the element's Legendre expansion (sum_n w_n
 //           xi_{d,n} u_n / sum_n w_n xi_{d,n}^2, mirror nodes paired so that a constant
@@ -13,9 +13,10 @@
 //           where |s - s~| exceeds kLimEps times the component's scale (the average
 //           energy E = |tau + D c^2| over c^2 for D, over c for S, E for tau); where
 //           theta < 1 every node moves to ubar + theta (u - ubar).  Then the
-//           physicality operator (Sec. 2.5) and the recovery of the next stage's
-//           primitives, all before one write of U and W.  One factor for all
-//           components keeps every node on the segment to the (admissible) average.
+//           physicality operator (Sec. 2.5); U and the next stage's primitives are
+//           written only for the nodes that changed (the stage launch wrote both for
+//           every node).  One factor for all components keeps every node on the
+//           segment to the (admissible) average.
 //
 // Workgroup layout of the operator kernel: EPB consecutive elements, one node per
 // lane; the (direction, component) pairs of an element are spread over its lanes,
@@ -93,9 +94,11 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
   const bool act = e < m.nelem;
   const long long g = e * NPE + node;
   const long long ne = m.nelem;
-  double u[NV];
+  double u[NV], u0[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = act ? a.U[v * m.ntot + g] : 1.0;
+  for (int v = 0; v < NV; ++v) u[v] = u0[v] = act ? a.U[v * m.ntot + g] : 1.0;
+  // the density the stage launch recovered (NaN where its recovery failed), loaded with U
+  const double rho_stage = (act && a.Wout) ? a.Wout[g] : 0.0;
   // this lane's pairs: own and neighbour averages, and the element's energy scale
   double ub[KP], up[KP], um[KP];
   double E = 0.0;
@@ -156,16 +159,30 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
   }
   if (a.phys) physicality_block_t<DIM, P, NT>(u, act, tid, el, node, a.t, a.q, counter_slot(a.cnt), sbuf, sflag, svote);
   if (!act) return;
+  // only the nodes the limiter or the operator changed are written (NaN compares unequal)
+  bool changed = false;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) a.U[v * m.ntot + g] = u[v];
+  for (int v = 0; v < NV; ++v) changed = changed || !(u[v] == u0[v]);
+  if (changed) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.U[v * m.ntot + g] = u[v];
+  }
   if (a.Wout) {
-    // started as outside a stage: reading the stage input's primitives for a warm start
-    // cost more (one more state read) than the iterations it saved
-    double w[NV];
-    const int st = con2prim<EOS, DIM>(u, w, a.q);
-    count_c2p(counter_slot(a.cnt), st, e);
+    // the stage launch recovered every node; recover again (and count) the changed nodes,
+    // Newton started from the stage's primitives, and the nodes whose recovery failed
+    // there (marked by a NaN density), from the usual start
+    const bool marked = !(rho_stage == rho_stage);
+    if (changed || marked) {
+      double w[NV], wp[NV];
+      if (!marked) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a.Wout[v * m.ntot + g] = w[v];
+        for (int v = 0; v < NV; ++v) wp[v] = a.Wout[v * m.ntot + g];
+      }
+      const int st = con2prim<EOS, DIM>(u, w, a.q, marked ? nullptr : wp);
+      count_c2p(counter_slot(a.cnt), st, e);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.Wout[v * m.ntot + g] = w[v];
+    }
   }
 }
 
