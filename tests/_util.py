@@ -43,6 +43,7 @@ AMPLIFIED_BARS = {
     "kh_tm 9x8 p=3 dt x300 1 step": 3e-11,     # 6.0e-12 .. 8.4e-12
     "riemann2d test 1 16x16 p=1 step": 1e-11,  # 2.7e-13 .. 2.6e-12 per step from the oracle's state
     "blast2d 24x24 p=2 limited step": 5e-12,   # up to 1.2e-12 (the limiter's factor from cancelling averages)
+    "kh_tm 1x1 p=3 limited 2 steps": 3e-12,    # 4.8e-13 (one element, its own neighbour on every side)
 }
 
 # Parity bars.  Two correct FP64 evaluations of the DG operator differ by a modest

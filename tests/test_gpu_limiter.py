@@ -179,6 +179,43 @@ def test_fp32_form_with_the_limiter():
     assert rel <= 1e-5
 
 
+DEGENERATE = [
+    ("kh_tm", {"n_elem": (1, 1, 1), "bc": (wl.PERIODIC, wl.PERIODIC, wl.PERIODIC)}),
+    ("kh_tm", {"n_elem": (1, 7, 1)}),
+    ("kh_tm", {"n_elem": (9, 1, 1), "bc": (wl.PERIODIC, wl.REFLECT, wl.PERIODIC)}),
+    ("wave1d", {"n_elem": (1, 1, 1)}),
+    ("wave1d", {"n_elem": (3, 1, 1), "p": 1}),
+]
+
+
+@pytest.mark.parametrize("kind,over", DEGENERATE)
+def test_limiter_on_degenerate_meshes(kind, over):
+    """Two limited SSP-RK3 steps on a single element (its own periodic neighbour on every
+    side), meshes one element wide and mostly empty tiles, against the oracle, with the
+    same number of limited elements."""
+    from paper_2205_00095_amd.solver import Solver
+    from ._util import oracle_state
+    cfg = wl.make_config(kind, **over)
+    cfg.update(precision=wl.FP64, limiter=1)
+    print(f"case {kind} {over} with the limiter", flush=True)
+    st, U = oracle_state(cfg)
+    stats = {}
+    U_ref = U
+    for _ in range(2):
+        U_ref = ots.step(U_ref, cfg["dt"], st, stats=stats)
+    _, bar, _ = step_bar(U, cfg["dt"], 2, st)
+    if kind == "kh_tm" and over["n_elem"] == (1, 1, 1):
+        bar = torch.clamp(bar, min=AMPLIFIED_BARS["kh_tm 1x1 p=3 limited 2 steps"])
+    s = Solver(cfg)
+    Ud = U.cuda().contiguous()
+    s.run(Ud, cfg["dt"], 2)
+    d = s.diagnostics()
+    err = rel_err_per_var(Ud.cpu(), U_ref)
+    print(f"err {err.tolist()} bar {bar.tolist()} gpu {d} oracle {stats}", flush=True)
+    assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
+    assert d["limited"] == stats.get("limited", 0) and d["c2p_fail"] == 0
+
+
 def test_order_zero_ignores_the_limiter():
     """At p = 0 the limiter has nothing to limit: a run with it is bit-identical to one without."""
     from paper_2205_00095_amd.solver import Solver
