@@ -29,7 +29,7 @@ namespace dgsrhd {
 struct LimArgs {
   double* U;             // stage output, limited in place
   const double* avg;     // [NV][nelem] averages of U (written by the stage launch)
-  double* Wout;          // primitives of the limited state, or null
+  double* Wout;          // the next stage's primitives (written by the stage launch), or null
   double xi[kMaxN1];     // reference nodes on [-1, 1]
   double inv_den;        // 1 / sum_n w_n xi_{d,n}^2 (the same for every d)
   int phys;
