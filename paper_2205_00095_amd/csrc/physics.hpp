@@ -376,20 +376,31 @@ __host__ __device__ __forceinline__ void tm_cubic_scaled(double X, double Y, dou
 // largest root by the closed form of the monic cubic evaluated in FP32 (relative error
 // ~1e-6 away from a double root; three FP64 Newton steps then reach rounding level, and
 // the caller accepts the result only when the last step is that small).
+// FP32 pieces of that start on the device: the hardware reciprocal, square root, log2
+// and exp2 (about one ulp each; the FP64 Newton steps absorb it), the cube root as
+// exp2(log2|y| / 3) with the sign of y.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ float start_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float start_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float start_cbrt(float y) {
+  return copysignf(__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fabsf(y)) * (1.0f / 3.0f)), y);
+}
+#else
+__host__ __forceinline__ float start_rcp(float x) { return 1.0f / x; }
+__host__ __forceinline__ float start_sqrt(float x) { return sqrtf(x); }
+__host__ __forceinline__ float start_cbrt(float y) { return cbrtf(y); }
+#endif
+
 __host__ __device__ __forceinline__ double tm_cubic_start_f32(double A, double C1, double C2, double C3) {
-  const float ia = 1.0f / (float)A;
+  const float ia = start_rcp((float)A);
   const float c1 = (float)C1 * ia, c2 = (float)C2 * ia, c3 = (float)C3 * ia;
   const float Q = (3.0f * c2 - c1 * c1) * (1.0f / 9.0f);
   const float R = (9.0f * c1 * c2 - 27.0f * c3 - 2.0f * c1 * c1 * c1) * (1.0f / 54.0f);
   const float dd = Q * Q * Q + R * R;
   float W;
   if (dd < 0.0f) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    const float irq = rsqrtf(-Q * Q * Q);
-#else
-    const float irq = 1.0f / sqrtf(-Q * Q * Q);
-#endif
-    const float x = fminf(1.0f, fmaxf(-1.0f, R * irq));
+    const float sq = start_sqrt(-Q);
+    const float x = fminf(1.0f, fmaxf(-1.0f, R * start_rcp(-Q * sq)));
     float t;
     if (x > -0.9f) {
       // cos(acos(x) / 3): the fit of cos_third_acos and two Newton steps on 4 t^3 - 3 t = x
@@ -397,15 +408,15 @@ __host__ __device__ __forceinline__ double tm_cubic_start_f32(double A, double C
 #pragma unroll
       for (int it = 0; it < 2; ++it) {
         const float t2 = t * t;
-        t -= (t * (4.0f * t2 - 3.0f) - x) / (12.0f * t2 - 3.0f);
+        t -= (t * (4.0f * t2 - 3.0f) - x) * start_rcp(12.0f * t2 - 3.0f);
       }
     } else {
       t = cosf(acosf(x) * (1.0f / 3.0f));
     }
-    W = 2.0f * sqrtf(-Q) * t - c1 * (1.0f / 3.0f);
+    W = 2.0f * sq * t - c1 * (1.0f / 3.0f);
   } else {
-    const float sd = sqrtf(dd);
-    W = -c1 * (1.0f / 3.0f) + cbrtf(R + sd) + cbrtf(R - sd);
+    const float sd = start_sqrt(dd);
+    W = -c1 * (1.0f / 3.0f) + start_cbrt(R + sd) + start_cbrt(R - sd);
   }
   return (double)W;
 }
