@@ -66,12 +66,14 @@ constexpr double kLimEps = 1e-10;
 
 // neighbour of element (x, y, z) along d on side dir, or the element itself at a
 // non-periodic end
-__device__ __forceinline__ int neighbour_or_self(const MeshArgs& m, const int* c, int e, int d, int dir) {
+// (selects rather than arrays indexed by the per-lane direction, which could go to scratch)
+__device__ __forceinline__ int neighbour_or_self(const MeshArgs& m, int cx, int cy, int cz, int e, int d, int dir) {
   const int n = d == 0 ? m.nex : (d == 1 ? m.ney : m.nez);
   const int stride = d == 0 ? 1 : (d == 1 ? m.nex : m.nex * m.ney);
-  const int k = c[d] + dir;
-  if (k < 0) return m.periodic[d] ? e + (n - 1) * stride : e;
-  if (k >= n) return m.periodic[d] ? e - (n - 1) * stride : e;
+  const int per = d == 0 ? m.periodic[0] : (d == 1 ? m.periodic[1] : m.periodic[2]);
+  const int k = (d == 0 ? cx : (d == 1 ? cy : cz)) + dir;
+  if (k < 0) return per ? e + (n - 1) * stride : e;
+  if (k >= n) return per ? e - (n - 1) * stride : e;
   return e + dir * stride;
 }
 
@@ -104,7 +106,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
   double E = 0.0;
   if (act) {
     const int ie = (int)e;
-    const int c[3] = {ie % m.nex, (ie / m.nex) % m.ney, ie / (m.nex * m.ney)};
+    const int cx = ie % m.nex, cy = (ie / m.nex) % m.ney, cz = ie / (m.nex * m.ney);
 #pragma unroll
     for (int j = 0; j < KP; ++j) {
       const int k = node + j * NPE;
@@ -113,8 +115,8 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
         const int d = k / NV, v = k % NV;
         const double* av = a.avg + v * ne;
         ub[j] = av[e];
-        up[j] = av[neighbour_or_self(m, c, ie, d, +1)];
-        um[j] = av[neighbour_or_self(m, c, ie, d, -1)];
+        up[j] = av[neighbour_or_self(m, cx, cy, cz, ie, d, +1)];
+        um[j] = av[neighbour_or_self(m, cx, cy, cz, ie, d, -1)];
       }
     }
     if (node < NS) E = fabs(a.avg[(NV - 1) * ne + e] + a.avg[e] * a.q.c2);
@@ -178,7 +180,9 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) wp[v] = a.Wout[v * m.ntot + g];
       }
-      const int st = con2prim<EOS, DIM>(u, w, a.q, marked ? nullptr : wp);
+      // (two calls rather than one through a selected pointer, which would put the start
+      // in scratch memory)
+      const int st = marked ? con2prim<EOS, DIM>(u, w, a.q) : con2prim<EOS, DIM>(u, w, a.q, wp);
       count_c2p(counter_slot(a.cnt), st, e);
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.Wout[v * m.ntot + g] = w[v];
