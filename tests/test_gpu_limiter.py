@@ -162,10 +162,11 @@ def test_limited_steps_match_oracle(case, monkeypatch):
 def test_fp32_form_with_the_limiter():
     """The FP32-contraction form under the limiter (the limiter itself, the operator and
     the recovery stay FP64): 20 steps of the 48x48 p=3 blast stay admissible and within
-    1e-5 (L1, relative) of the FP64 run."""
+    1e-5 (L1, relative) of the FP64 run; the matrix-core sweeps give the vector form's
+    result bit for bit."""
     from paper_2205_00095_amd.solver import Solver
     out = []
-    for prec in (wl.FP64, wl.FP32_CONTRACT):
+    for prec in (wl.FP64, wl.FP32_CONTRACT, wl.FP32_MFMA):
         cfg, prims = _workload("blast2d", n_elem=(48, 48, 1), p=3, precision=prec)
         s = Solver(cfg)
         U = s.set_state(torch.from_numpy(prims).cuda())
@@ -177,6 +178,7 @@ def test_fp32_form_with_the_limiter():
     rel = float((out[1] - out[0]).abs().sum() / out[0].abs().sum())
     print(f"L1 relative difference FP32 form vs FP64: {rel:.2e}", flush=True)
     assert rel <= 1e-5
+    assert torch.equal(out[2], out[1])
 
 
 DEGENERATE = [
