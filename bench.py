@@ -731,6 +731,16 @@ def cpu_baseline(kind="kh_tm", steps=3, seconds=10.0):
     ref = _cpu_reference_runs()
     rates = {k: {"dof_stage_per_s": wl.n_dof(wl.make_config(k)) * n * 3 / sec, "steps": n, "s": sec}
              for k, (U_, sec, n) in ref.items()}
+    # the oracle's limited step (slope limiter and operator after every stage) on the
+    # cylindrical blast, a 128x128 p=2 sample of the limiter leg's 512x512 mesh
+    bcfg = wl.make_config("blast2d", n_elem=(128, 128, 1))
+    bst = Setup.from_config(bcfg)
+    brho, bv, bP = (torch.from_numpy(x) for x in wl.initial_primitives(bcfg))
+    bU = srhd.prim3_to_cons(brho, bv, bP, bst).reshape((bst.nvar,) + wl.field_shape(bcfg))
+    t1 = time.perf_counter()
+    timestep.run(bU, bcfg["dt"], 2, bst)
+    bsec = time.perf_counter() - t1
+    rates["blast2d_limited_128"] = {"dof_stage_per_s": wl.n_dof(bcfg) * 2 * 3 / bsec, "steps": 2, "s": bsec}
     rec = {"value": dofs * steps * 3 / dt, "unit": "DOF-stage/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} SSP-RK3 steps of the full {cfg['n_elem'][0]}x{cfg['n_elem'][1]} p={cfg['p']} "
