@@ -251,6 +251,12 @@ __host__ __device__ __forceinline__ void hll_flux(const double* WL, const double
 // U*_K = (lambda_K U_K - F_K + p* (0, e_d, lambda*)) / (lambda_K - lambda*) and the flux
 // F_K + lambda_K (U*_K - U_K): F_L, F*_L, F*_R or F_R by the signs of lambda_L,
 // lambda*, lambda_R.
+//
+// Evaluated with two divisions: the outer speeds stay fractions n / den (den > 0) as in
+// hll_flux; the HLL state and flux are kept multiplied by Delta = (lambda_R - lambda_L)
+// den_L den_R > 0, which leaves lambda* unchanged (the quadratic is homogeneous in
+// them) and scales p* by Delta; and with lambda_K = n / den,
+//   F*_K = F_K + n (lambda* U_K - F_K + p* (0, e_d, lambda*)) / (n - lambda* den).
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void hllc_flux(const double* WL, const double* WR, int d, const PhysParams& q,
                                           double* Fh) {
@@ -261,38 +267,44 @@ __host__ __device__ __forceinline__ void hllc_flux(const double* WL, const doubl
   double FL[NV], FR[NV];
   flux_dir<EOS, DIM>(WL, sL, d, FL);
   flux_dir<EOS, DIM>(WR, sR, d, FR);
-  double lmL, lpL, lmR, lpR;
-  wavespeeds<EOS, DIM>(WL, sL, d, q, lmL, lpL);
-  wavespeeds<EOS, DIM>(WR, sR, d, q, lmR, lpR);
-  const double aL = fmin(lmL, lmR), aR = fmax(lpL, lpR);
-  if (aL >= 0.0) {
+  double nmL, npL, dnL, nmR, npR, dnR;
+  wavespeeds_nd<EOS, DIM>(WL, sL, d, q, nmL, npL, dnL);
+  wavespeeds_nd<EOS, DIM>(WR, sR, d, q, nmR, npR, dnR);
+  // lambda_L = nA / dA (the lesser lambda_-), lambda_R = nB / dB (the greater lambda_+)
+  const bool lminL = nmL * dnR <= nmR * dnL;
+  const double nA = lminL ? nmL : nmR, dA = lminL ? dnL : dnR;
+  const bool lmaxL = npL * dnR >= npR * dnL;
+  const double nB = lmaxL ? npL : npR, dB = lmaxL ? dnL : dnR;
+  if (nA >= 0.0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) Fh[k] = FL[k];
     return;
   }
-  // HLL state and flux of the rows the contact needs (D, S_d, tau)
-  const double ih = 1.0 / (aR - aL);
+  // Delta times the HLL state and flux of the rows the contact needs (D, S_d, tau)
+  const double cA = nA * dB, cB = nB * dA, cAB = dA * dB, cU = nA * nB;
+  const double Dl = cB - cA;
   const double ULs = comp<DIM>(sL.U + 1, d), URs = comp<DIM>(sR.U + 1, d);
   const double FLs = comp<DIM>(FL + 1, d), FRs = comp<DIM>(FR + 1, d);
-  const double UhD = (aR * sR.U[0] - aL * sL.U[0] + FL[0] - FR[0]) * ih;
-  const double UhS = (aR * URs - aL * ULs + FLs - FRs) * ih;
-  const double UhT = (aR * sR.U[NV - 1] - aL * sL.U[NV - 1] + FL[NV - 1] - FR[NV - 1]) * ih;
-  const double FhD = (aR * FL[0] - aL * FR[0] + aL * aR * (sR.U[0] - sL.U[0])) * ih;
-  const double FhS = (aR * FLs - aL * FRs + aL * aR * (URs - ULs)) * ih;
-  const double FhT = (aR * FL[NV - 1] - aL * FR[NV - 1] + aL * aR * (sR.U[NV - 1] - sL.U[NV - 1])) * ih;
+  const double UhD = cB * sR.U[0] - cA * sL.U[0] + cAB * (FL[0] - FR[0]);
+  const double UhS = cB * URs - cA * ULs + cAB * (FLs - FRs);
+  const double UhT = cB * sR.U[NV - 1] - cA * sL.U[NV - 1] + cAB * (FL[NV - 1] - FR[NV - 1]);
+  const double FhD = cB * FL[0] - cA * FR[0] + cU * (sR.U[0] - sL.U[0]);
+  const double FhS = cB * FLs - cA * FRs + cU * (URs - ULs);
+  const double FhT = cB * FL[NV - 1] - cA * FR[NV - 1] + cU * (sR.U[NV - 1] - sL.U[NV - 1]);
   const double Eh = UhT + q.c2 * UhD, FEh = FhT + q.c2 * FhD;
   const double b = Eh + FhS;
   const double disc = fmax(b * b - 4.0 * FEh * UhS, 0.0);
   const double lam = 2.0 * q.c2 * UhS / (b + sqrt(disc));
-  const double ps = FhS - lam * FEh * q.inv_c2;
+  const double ps = FhS - lam * FEh * q.inv_c2;  // Delta p*
   const bool left = lam >= 0.0;
-  if (!left && !(aR > 0.0)) {
+  if (!left && !(nB > 0.0)) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) Fh[k] = FR[k];
     return;
   }
-  const double a = left ? aL : aR;
-  const double ia = 1.0 / (a - lam);
+  const double n = left ? nA : nB, dn = left ? dA : dB;
+  const double r = n / (Dl * (n - lam * dn));
+  const double nr = r * Dl;  // n / (n - lambda* den)
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const double U = left ? sL.U[k] : sR.U[k];
@@ -302,8 +314,7 @@ __host__ __device__ __forceinline__ void hllc_flux(const double* WL, const doubl
 #pragma unroll
     for (int j = 0; j < DIM; ++j)
       if (k == 1 + j && j == d) extra = ps;
-    const double Us = (a * U - F + extra) * ia;
-    Fh[k] = F + a * (Us - U);
+    Fh[k] = F + nr * (lam * U - F) + r * extra;
   }
 }
 
