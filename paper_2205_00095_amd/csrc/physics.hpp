@@ -47,10 +47,6 @@ __host__ __device__ __forceinline__ double h_excess(double th, const PhysParams&
   }
 }
 
-// Component d of a DIM-vector stored from v[0], for a direction known only at run
-// time: a chain of selects over values.  An indexed access would move the array to
-// scratch memory, and so would the optimiser's folding of a select of two loads into
-// one indexed load, which the empty asm (device pass only) hides the loads from.
 // 1 / sqrt(x): the device's reciprocal square root (one refined v_rsq), the plain
 // quotient on the host
 __host__ __device__ __forceinline__ double inv_sqrt(double x) {
@@ -72,6 +68,22 @@ __host__ __device__ __forceinline__ double sqrt_pos(double x) {
 #endif
 }
 
+// 1 / x to about 2^-44 relative: the device's reciprocal with one Newton refinement
+// (a quotient to that accuracy is enough for a Newton step that is not the last);
+// the plain quotient on the host
+__host__ __device__ __forceinline__ double rcp_refined(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(fma(-x, r, 1.0), r, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// Component d of a DIM-vector stored from v[0], for a direction known only at run
+// time: a chain of selects over values.  An indexed access would move the array to
+// scratch memory, and so would the optimiser's folding of a select of two loads into
+// one indexed load, which the empty asm (device pass only) hides the loads from.
 __host__ __device__ __forceinline__ double opaque(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   asm("" : "+v"(x));
@@ -627,12 +639,13 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
         } else {
           Wn = tm_cubic_start_f32(A, C1, C2, C3);
         }
+        // (the first two steps with a refined reciprocal of f', the last with the quotient)
         double step = 0.0;
 #pragma unroll
         for (int it = 0; it < 3; ++it) {
           const double f = ((A * Wn + C1) * Wn + C2) * Wn + C3;
           const double fp = (3.0 * A * Wn + 2.0 * C1) * Wn + C2;
-          step = f / fp;
+          step = it < 2 ? f * rcp_refined(fp) : f / fp;
           Wn -= step;
         }
         const double fp = (3.0 * A * Wn + 2.0 * C1) * Wn + C2;
@@ -681,10 +694,14 @@ __host__ __device__ __forceinline__ int con2prim(const double* U, double* W, con
       gb = sqrt_pos(Wc);  // gamma beta
       const double beta = gb * ig;
       rho = D * ig;
-      // P = (X^2 - (rho c^2)^2)/(3X), X = E - M.v, via X_ = X - rho c^2
-      const double Xm = tau - Smag * beta * q.c + D * q.c2 * Wc * ig / (gam + 1.0);
-      const double X = Xm + rho * q.c2;
-      P = Xm * (Xm + 2.0 * rho * q.c2) / (3.0 * X);
+      // P = (X^2 - (rho c^2)^2)/(3X), X = E - M.v, via X_ = X - rho c^2 =
+      // tau - |S| beta c + D c^2 (gamma^2 - 1) / (gamma (gamma + 1)), carried as
+      // N = X_ (gamma + 1) so that one division remains:
+      // P = N (N + 2 rho c^2 (gamma + 1)) / (3 (gamma + 1) (N + rho c^2 (gamma + 1)))
+      const double gp1 = gam + 1.0;
+      const double N = (tau - Smag * beta * q.c) * gp1 + D * q.c2 * Wc * ig;
+      const double rc2g = rho * q.c2 * gp1;
+      P = N * (N + 2.0 * rc2g) / (3.0 * gp1 * (N + rc2g));
     }
     if (!(P > 0.0) || !isfinite(P) || !isfinite(rho)) {
       if (status == C2P_OK) status = C2P_BADP;
