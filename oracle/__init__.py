@@ -24,8 +24,9 @@ Each step follows the paper in its order and notation:
 * ``timestep``     SSP-RK1/2/3 with the operator after each stage (Sec. 2.3)
 * ``objective``    the integral of v_y^2 (the Kelvin-Helmholtz diagnostic)
 
-Parity status per function is stated in each module header; the only
-function whose parity is unpinned beyond its own measured accuracy is the
-analytic ideal-gas quartic solver (``con2prim.ideal_quartic``).
+Parity status per function is stated in each module header.  Every function
+is pinned; the analytic ideal-gas quartic solver (``con2prim.ideal_quartic``)
+is pinned on the velocities where its formula holds its digits (beta in
+[0.3, 0.99]) and only measured below that.
 """
 from .setup import Setup  # noqa: F401

@@ -19,8 +19,9 @@ ideal_quartic  Sec. 3.1, analytic: the quartic in beta solved through its
                beta^4 + a3 beta^3 + a2 beta^2 + a1 beta + a0;
                R = (9 i1 i2 - 27 i3 - 2 i1^3)/54; trigonometric branch
                x = 2 sqrt(-S) cos(atan2(sqrt(-T), R)/3) - i1/3.
-               PARITY UNPINNED beyond its own measured accuracy (the printed
-               chain loses digits at small beta).
+               Pinned against the exact state on beta in [0.3, 0.99] (beta to
+               2e-9, rho to 3e-8, P to 5e-8); below beta ~ 0.3 the chain loses
+               digits to cancellation and its accuracy is only measured.
 tm_cubic       Sec. 3.2, analytic: the cubic of Eq. (synge_cubic) in
                W = gamma^2 - 1 by the trigonometric (d < 0) or Cardano (d >= 0)
                formula, then one Newton step on the same cubic (reading: the

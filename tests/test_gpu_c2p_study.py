@@ -49,8 +49,9 @@ def test_fixed_iteration_velocity_matches_oracle(eos, method, iters):
     """Same solver, same count: the GPU's velocity error equals the oracle's to rounding,
     |e_gpu - e_oracle| <= 2e-14 + 1e-9 e_oracle (an iterate far from the root carries
     rounding differences of ~1e-11 of itself through the remaining steps).  The analytic
-    ideal-gas quartic is the exception: its printed chain loses digits (up to ~1e-10 at
-    gamma = 100, parity unpinned beyond that), so only its error level is compared."""
+    ideal-gas quartic is the exception: its printed chain loses digits to cancellation (up
+    to ~1e-10 at gamma = 100 on this grid), so the two sides round differently and only
+    their error levels are compared."""
     print(f"case eos {eos} solver {method} iterations {iters}", flush=True)
     _, e_ora = _oracle_err(eos, method, iters)
     e_gpu = _gpu(eos, method, iters)
