@@ -159,6 +159,52 @@ def test_limited_steps_match_oracle(case, monkeypatch):
     assert total > 0  # the limiter acted in every case
 
 
+@pytest.mark.parametrize("order", [3, 2])
+def test_limited_steps_through_an_inadmissible_element(order, monkeypatch):
+    """One element of the blast with D = -1 at every node: its recovery fails in every
+    stage (the floor state, counted), the stage launch marks those nodes, the limiter
+    launch leaves the element unchanged (its average is inadmissible, counted) and
+    recovers the marked nodes again from the usual start (failing again, counted).  Two
+    steps from the oracle's state each: the state within the step bar (the oracle's
+    1-ulp response here is at most 3.1e-13), and 9 failed recoveries and one
+    inadmissible average per stage, as in the oracle."""
+    from paper_2205_00095_amd.solver import Solver
+    cfg, prims = _workload("blast2d", n_elem=(12, 12, 1))
+    st = Setup.from_config(cfg)
+    P = torch.from_numpy(prims)
+    nv = st.nvar
+    U = srhd.prim3_to_cons(P[0], P[1:nv - 1], P[nv - 1], st).contiguous()
+    U[0, 0, 6, 5] = -1.0
+    dt = cfg["dt"]
+    ties = [0]
+    limit0 = olim.limit
+
+    def counting(V, st_, stats=None):
+        ties[0] += _near_ties(V, st_)
+        return limit0(V, st_, stats)
+    monkeypatch.setattr(olim, "limit", counting)
+    s = Solver(cfg, sync=False)
+    for k in range(2):
+        print(f"case inadmissible element, order {order}: step {k} from the oracle's state", flush=True)
+        stats = {}
+        ties[0] = 0
+        U_next = ots.step(U, dt, st, phys=True, stats=stats, order=order)
+        _, bar, _ = step_bar(U, dt, 1, st, order=order)
+        Ud = U.cuda().contiguous()
+        s.reset_diagnostics()
+        s.step(Ud, dt, order=order)
+        d = s.diagnostics()
+        err = rel_err_per_var(Ud.cpu(), U_next)
+        print(f"err {err.tolist()} bar {bar.tolist()} gpu {d} oracle {stats}", flush=True)
+        assert bool((err <= bar).all()), (err.tolist(), bar.tolist())
+        assert d["c2p_fail"] == stats["c2p_fail"] == 9 * order
+        assert d["bad_average"] == stats["bad_average"] == order
+        assert d["flagged"] == stats["flagged"] and d["smoothed"] == stats.get("smoothed", 0)
+        assert abs(d["limited"] - stats.get("limited", 0)) <= ties[0]
+        assert float(U_next[0, 0, 6, 5].max()) < 0.0  # the element is still inadmissible
+        U = U_next
+
+
 def test_fp32_form_with_the_limiter():
     """The FP32-contraction form under the limiter (the limiter itself, the operator and
     the recovery stay FP64): 20 steps of the 48x48 p=3 blast stay admissible and within
