@@ -137,6 +137,42 @@ def test_con2prim_matches_oracle(eos, method, tol):
     assert float((du / umag).max()) <= tol
 
 
+@pytest.mark.parametrize("gamma_ad", [4.0 / 3.0, 5.0 / 3.0])
+def test_con2prim_quartic_on_its_accurate_range(gamma_ad):
+    """The analytic ideal-gas quartic on the velocities where its formula keeps its digits
+    (beta in [0.3, 0.99], Theta/c^2 in [1e-3, 1e3], random directions): the GPU recovers
+    the exact state to the bounds that pin the oracle's (beta 2e-9, rho 3e-8, P 5e-8) and
+    agrees with the oracle to their sum."""
+    rng = np.random.default_rng(41)
+    n = 64 * 6 + 13
+    beta = rng.uniform(0.3, 0.99, n)
+    rho = 10 ** rng.uniform(-2, 2, n)
+    P = rho * 10 ** rng.uniform(-3, 3, n)
+    nv = rng.standard_normal((3, n))
+    nv /= np.linalg.norm(nv, axis=0)
+    cfg = wl.make_config("random3d", n_elem=(n, 1, 1), p=0, eos=IDEAL, c2p=QUARTIC, gamma_ad=gamma_ad)
+    st = Setup.from_config(cfg)
+    U = osrhd.prim3_to_cons(torch.tensor(rho), torch.tensor(nv * beta), torch.tensor(P), st)
+    U = U.reshape((5,) + wl.field_shape(cfg))
+    W_ref, status = ocp.con2prim(U, st)
+    assert int((status != 0).sum()) == 0
+    print(f"case quartic, Gamma {gamma_ad:.4f}, {n} states", flush=True)
+    s = _solver(cfg)
+    W = s.con2prim(U.cuda()).cpu().reshape(5, -1)
+    W_ref = W_ref.reshape(5, -1)
+    u = W[1:4]
+    vrec = (torch.sqrt((u ** 2).sum(0)) / torch.sqrt(1 + (u ** 2).sum(0))).numpy()
+    assert (np.abs(vrec - beta) / beta).max() < 2e-9
+    assert (np.abs(W[0].numpy() - rho) / rho).max() < 3e-8
+    assert (np.abs(W[4].numpy() - P) / P).max() < 5e-8
+    rel = (W - W_ref).abs() / W_ref.abs().clamp(min=1e-300)
+    ur = W_ref[1:4]
+    vref = (torch.sqrt((ur ** 2).sum(0)) / torch.sqrt(1 + (ur ** 2).sum(0))).numpy()
+    # (compared in beta: an error in beta reaches u = gamma beta amplified by gamma^2)
+    assert float(rel[0].max()) <= 6e-8 and float(rel[4].max()) <= 1e-7
+    assert (np.abs(vrec - vref) / vref).max() <= 4e-9
+
+
 def test_con2prim_paper_grid_c3e8():
     """The paper's 25x25 grid at c = 3e8 (SI units) through the GPU solvers."""
     c = 3.0e8
