@@ -139,7 +139,7 @@ typedef struct {
   long long bad_average;     /* flagged elements left unchanged (inadmissible average) */
   long long bad_input;       /* dg_set_state nodes rejected */
   long long first_bad_elem;  /* lowest element index with a recovery failure, or -1 */
-  long long limited;         /* (element, component) pairs replaced by the slope limiter */
+  long long limited;         /* element-stages the slope limiter scaled (theta < 1) */
 } dg_diag;
 
 /* Create a context for one mesh.  Validates desc, builds the basis tables on the
