@@ -12,12 +12,12 @@ namespace {
 
 template <int DIM, int P>
 hipError_t run_limiter(int eos, const LimArgs& a, hipStream_t s) {
-  using G = Geo<DIM, P>;
-  const int nb = (a.m.nelem + G::EPB - 1) / G::EPB;
+  using L = LimGeo<DIM, P>;
+  const int nb = (a.m.nelem + L::EPB - 1) / L::EPB;
   if (eos == EOS_IDEAL)
-    hipLaunchKernelGGL((k_limit<DIM, P, EOS_IDEAL>), dim3(nb), dim3(G::NT), 0, s, a);
+    hipLaunchKernelGGL((k_limit<DIM, P, EOS_IDEAL>), dim3(nb), dim3(L::NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_limit<DIM, P, EOS_TM>), dim3(nb), dim3(G::NT), 0, s, a);
+    hipLaunchKernelGGL((k_limit<DIM, P, EOS_TM>), dim3(nb), dim3(L::NT), 0, s, a);
   return hipGetLastError();
 }
 

@@ -18,9 +18,11 @@
 //           every node).  One factor for all components keeps every node on the
 //           segment to the (admissible) average.
 //
-// Workgroup layout of the operator kernel: EPB consecutive elements, one node per
-// lane; the (direction, component) pairs of an element are spread over its lanes,
-// whose average loads are issued before the first barrier.
+// Workgroup layout: four waves, each holding EPW = 64 / NPE whole elements (one node
+// per lane, the lanes past EPW * NPE idle), so that every exchange among an element's
+// nodes stays inside one wave and needs no workgroup barrier; each lane has its own
+// LDS slot (its thread index).  The (direction, component) pairs of an element are
+// spread over its lanes, whose average loads are issued with the state's.
 #pragma once
 #include "kernels.hpp"
 
@@ -77,23 +79,89 @@ __device__ __forceinline__ int neighbour_or_self(const MeshArgs& m, int cx, int 
   return e + dir * stride;
 }
 
-template <int DIM, int P, int EOS>
-__global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
+template <int DIM, int P>
+struct LimGeo {
   using G = Geo<DIM, P>;
-  constexpr int NV = G::NV, NPE = G::NPE, NT = G::NT, EPB = G::EPB, N1 = G::N1;
-  constexpr int NS = DIM * NV;               // (direction, component) pairs per element
+  static constexpr int NPE = G::NPE, NV = G::NV, N1 = G::N1;
+  static constexpr int EPW = 64 / NPE;  // whole elements per wave
+  static constexpr int NT = 256;        // four waves
+  static constexpr int EPB = 4 * EPW;   // elements per workgroup
+  static constexpr int NS = DIM * NV;   // (direction, component) pairs per element
+};
+
+// Ordering of LDS data exchanged among the lanes of one wave: a wave's LDS accesses
+// execute in program order, so the compiler only has to keep that order.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The physicality operator (Sec. 2.5) on the elements of one wave: the steps and the
+// arithmetic order of physicality_block_t, with wave-scope ordering in place of its
+// workgroup barriers.  base: the LDS slot of the element's node 0; slot: this lane's.
+template <int DIM, int P>
+__device__ __forceinline__ void physicality_wave(double* Un, bool act, int slot, int base, int node, const Tables& t,
+                                                 const PhysParams& q, Counters* cnt, double* sbuf, int* sflag) {
+  using L = LimGeo<DIM, P>;
+  constexpr int NV = L::NV, NPE = L::NPE, NT = L::NT;
+  const bool bad = act && !admissible<DIM>(Un, q);
+  if (__ballot(bad) == 0ull) return;  // uniform across the wave
+  const double wn = node_weight<DIM, P>(t, node);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sbuf[v * NT + slot] = wn * Un[v];
+  sflag[slot] = bad ? 1 : 0;
+  wave_sync();
+  bool eflag = false;
+  if (act)
+    for (int n = 0; n < NPE; ++n) eflag |= (sflag[base + n] != 0);
+  double Ub[NV];
+  bool avg_ok = false;
+  double s = 1.0;
+  if (act && eflag) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+      for (int n = 0; n < NPE; ++n) acc += sbuf[v * NT + base + n];
+      Ub[v] = acc * t.inv_wsum;
+    }
+    avg_ok = admissible<DIM>(Ub, q);
+    if (avg_ok) s = node_factor<DIM>(Un, Ub, q);
+  }
+  const bool lead = act && eflag && node == 0;
+  count_wave(&cnt->flagged, lead);
+  count_wave(&cnt->smoothed, lead && avg_ok);
+  count_wave(&cnt->bad_average, lead && !avg_ok);
+  wave_sync();
+  sbuf[slot] = s;
+  wave_sync();
+  if (act && eflag && avg_ok) {
+    double smin = 1.0;
+    for (int n = 0; n < NPE; ++n) smin = fmin(smin, sbuf[base + n]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = smin * Un[v] + (1.0 - smin) * Ub[v];
+  }
+}
+
+template <int DIM, int P, int EOS>
+__global__ __launch_bounds__(256) void k_limit(LimArgs a) {
+  using L = LimGeo<DIM, P>;
+  constexpr int NV = L::NV, NPE = L::NPE, NT = L::NT, EPW = L::EPW, EPB = L::EPB, N1 = L::N1, NS = L::NS;
   constexpr int KP = (NS + NPE - 1) / NPE;   // pairs per lane
   __shared__ double sbuf[NV * NT];
   __shared__ double sratio[EPB * NS];
   __shared__ int sflag[NT];
-  __shared__ int svote[(NT + 63) / 64];
   const MeshArgs& m = a.m;
   const int tid = threadIdx.x;
-  const int el = tid / NPE, node = tid % NPE;
+  const int lane = tid & 63;
+  const int ew = lane / NPE, node = lane % NPE;
+  const bool lane_ok = ew < EPW;
+  const int el = (tid >> 6) * EPW + ew;  // element of the workgroup (lane_ok lanes)
+  const int base = tid - node;           // LDS slot of the element's node 0
   // XCD-aware order: each XCD takes a contiguous range of element groups, so the rows
   // of neighbour averages a group gathers are mostly in that XCD's L2 already
   const long long e = (long long)xcd_tile(blockIdx.x, gridDim.x) * EPB + el;
-  const bool act = e < m.nelem;
+  const bool act = lane_ok && e < m.nelem;
   const long long g = e * NPE + node;
   const long long ne = m.nelem;
   double u[NV], u0[NV];
@@ -123,16 +191,16 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) sbuf[v * NT + tid] = u[v];
-  __syncthreads();
+  wave_sync();
   // slope of each pair from the odd parts of the mirror pairs of nodes, minmod bound, ratio
 #pragma unroll
   for (int j = 0; j < KP; ++j) {
     const int k = node + j * NPE;
-    if (k < NS) {
+    if (lane_ok && k < NS) {
       double ratio = 1.0;
       if (act) {
         const int d = k / NV, v = k % NV;
-        const double* row = sbuf + v * NT + el * NPE;
+        const double* row = sbuf + v * NT + base;
         double acc = 0.0;
         for (int n = 0; n < NPE; ++n) {
           const double wx = node_weight<DIM, P>(a.t, n) * a.xi[node_coord<N1>(n, d)];
@@ -146,10 +214,12 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
       sratio[el * NS + k] = ratio;
     }
   }
-  __syncthreads();
+  wave_sync();
   double th = 1.0;
+  if (act) {
 #pragma unroll
-  for (int k = 0; k < NS; ++k) th = fmin(th, sratio[el * NS + k]);
+    for (int k = 0; k < NS; ++k) th = fmin(th, sratio[el * NS + k]);
+  }
   const bool lim = act && th < 1.0;
   count_wave(&counter_slot(a.cnt)->limited, lim && node == 0);
   if (lim) {
@@ -159,7 +229,9 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_limit(LimArgs a) {
       u[v] = avv + th * (u[v] - avv);
     }
   }
-  if (a.phys) physicality_block_t<DIM, P, NT>(u, act, tid, el, node, a.t, a.q, counter_slot(a.cnt), sbuf, sflag, svote);
+  // (sbuf is rewritten by the operator only after every lane of the wave has read its
+  // slopes: the reads above precede the ratio exchange's ordering point)
+  if (a.phys) physicality_wave<DIM, P>(u, act, tid, base, node, a.t, a.q, counter_slot(a.cnt), sbuf, sflag);
   if (!act) return;
   // only the nodes the limiter or the operator changed are written (NaN compares unequal)
   bool changed = false;
