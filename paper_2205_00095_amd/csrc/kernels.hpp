@@ -335,6 +335,79 @@ __device__ __forceinline__ bool physicality_block_t(double* Un, bool act, int ti
   return true;
 }
 
+// Ordering of LDS data exchanged among the lanes of one wave: a wave's LDS accesses
+// execute in program order, so the compiler only has to keep that order.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The operator on the elements of one wave, for layouts in which no element spans two
+// waves: the steps and the arithmetic order of physicality_block_t, with wave-scope
+// ordering in place of its workgroup barriers.  sbuf holds NV * NTB doubles and sflag
+// NTB ints; slot is this lane's slot in them, base the slot of its element's node 0.
+// Returns whether any node of the wave was flagged (uniform across the wave).
+template <int DIM, int P, int NTB>
+__device__ __forceinline__ bool physicality_wave(double* Un, bool act, int slot, int base, int node, const Tables& t,
+                                                 const PhysParams& q, Counters* cnt, double* sbuf, int* sflag) {
+  using G = Geo<DIM, P>;
+  constexpr int NV = G::NV, NPE = G::NPE, NT = NTB, N1 = G::N1;
+  const bool bad = act && !admissible<DIM>(Un, q);
+  if (__ballot(bad) == 0ull) return false;
+  double wn = t.w[node_coord<N1>(node, 0)];
+  if (DIM > 1) wn *= t.w[node_coord<N1>(node, 1)];
+  if (DIM > 2) wn *= t.w[node_coord<N1>(node, 2)];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sbuf[v * NT + slot] = wn * Un[v];
+  sflag[slot] = bad ? 1 : 0;
+  wave_sync();
+  bool eflag = false;
+  if (act)
+    for (int n = 0; n < NPE; ++n) eflag |= (sflag[base + n] != 0);
+  double Ub[NV];
+  bool avg_ok = false;
+  double s = 1.0;
+  if (act && eflag) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+      for (int n = 0; n < NPE; ++n) acc += sbuf[v * NT + base + n];
+      Ub[v] = acc * t.inv_wsum;
+    }
+    avg_ok = admissible<DIM>(Ub, q);
+    if (avg_ok) s = node_factor<DIM>(Un, Ub, q);
+  }
+  const bool lead = act && eflag && node == 0;
+  count_wave(&cnt->flagged, lead);
+  count_wave(&cnt->smoothed, lead && avg_ok);
+  count_wave(&cnt->bad_average, lead && !avg_ok);
+  wave_sync();
+  sbuf[slot] = s;
+  wave_sync();
+  if (act && eflag && avg_ok) {
+    double smin = 1.0;
+    for (int n = 0; n < NPE; ++n) smin = fmin(smin, sbuf[base + n]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = smin * Un[v] + (1.0 - smin) * Ub[v];
+  }
+  return true;
+}
+
+// The operator on a workgroup whose lanes hold consecutive elements (lane = element *
+// NPE + node): per wave when NPE divides 64 (no element spans two waves), else with
+// workgroup barriers.  Must be reached by all threads of the block.  Returns whether a
+// node was flagged in this lane's wave (per-wave form) or block.
+template <int DIM, int P, int NTB>
+__device__ __forceinline__ bool physicality_t(double* Un, bool act, int tid, int el, int node, const Tables& t,
+                                              const PhysParams& q, Counters* cnt, double* sbuf, int* sflag,
+                                              int* svote) {
+  if constexpr (64 % Geo<DIM, P>::NPE == 0)
+    return physicality_wave<DIM, P, NTB>(Un, act, tid, tid - node, node, t, q, cnt, sbuf, sflag);
+  else
+    return physicality_block_t<DIM, P, NTB>(Un, act, tid, el, node, t, q, cnt, sbuf, sflag, svote);
+}
+
 template <int DIM, int P>
 __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restrict__ U, MeshArgs m, Tables t,
                                                              PhysParams q, Counters* cnt) {
@@ -351,7 +424,7 @@ __global__ __launch_bounds__((Geo<DIM, P>::NT)) void k_enforce(double* __restric
   double u[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = act ? U[v * m.ntot + g] : 1.0;
-  physicality_block_t<DIM, P, NT>(u, act, tid, el, node, t, q, counter_slot(cnt), sbuf, sflag, svote);
+  physicality_t<DIM, P, NT>(u, act, tid, el, node, t, q, counter_slot(cnt), sbuf, sflag, svote);
   if (act) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) U[v * m.ntot + g] = u[v];
@@ -1014,13 +1087,13 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.Pout[v * ntot + g] = Un[v];
     }
-    // true when the operator ran on this tile; otherwise every node passed its
-    // admissibility test and the recovery need not repeat it
+    // true when the operator ran on this lane's wave (or tile); otherwise every node
+    // passed its admissibility test and the recovery need not repeat it
     bool changed = true;
     if (a.phys) {
       // sF was last read in the volume phase, before the face phase's closing barrier
-      changed = physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag, svote);
-      if (a.opflag && changed && tid == 0) *a.opflag = 1u;
+      changed = physicality_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag, svote);
+      if (a.opflag && changed && (tid & 63) == 0) *a.opflag = 1u;
     }
     if (act) {
       if (a.za != 0.0) {

@@ -89,60 +89,6 @@ struct LimGeo {
   static constexpr int NS = DIM * NV;   // (direction, component) pairs per element
 };
 
-// Ordering of LDS data exchanged among the lanes of one wave: a wave's LDS accesses
-// execute in program order, so the compiler only has to keep that order.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// The physicality operator (Sec. 2.5) on the elements of one wave: the steps and the
-// arithmetic order of physicality_block_t, with wave-scope ordering in place of its
-// workgroup barriers.  base: the LDS slot of the element's node 0; slot: this lane's.
-template <int DIM, int P>
-__device__ __forceinline__ void physicality_wave(double* Un, bool act, int slot, int base, int node, const Tables& t,
-                                                 const PhysParams& q, Counters* cnt, double* sbuf, int* sflag) {
-  using L = LimGeo<DIM, P>;
-  constexpr int NV = L::NV, NPE = L::NPE, NT = L::NT;
-  const bool bad = act && !admissible<DIM>(Un, q);
-  if (__ballot(bad) == 0ull) return;  // uniform across the wave
-  const double wn = node_weight<DIM, P>(t, node);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) sbuf[v * NT + slot] = wn * Un[v];
-  sflag[slot] = bad ? 1 : 0;
-  wave_sync();
-  bool eflag = false;
-  if (act)
-    for (int n = 0; n < NPE; ++n) eflag |= (sflag[base + n] != 0);
-  double Ub[NV];
-  bool avg_ok = false;
-  double s = 1.0;
-  if (act && eflag) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double acc = 0.0;
-      for (int n = 0; n < NPE; ++n) acc += sbuf[v * NT + base + n];
-      Ub[v] = acc * t.inv_wsum;
-    }
-    avg_ok = admissible<DIM>(Ub, q);
-    if (avg_ok) s = node_factor<DIM>(Un, Ub, q);
-  }
-  const bool lead = act && eflag && node == 0;
-  count_wave(&cnt->flagged, lead);
-  count_wave(&cnt->smoothed, lead && avg_ok);
-  count_wave(&cnt->bad_average, lead && !avg_ok);
-  wave_sync();
-  sbuf[slot] = s;
-  wave_sync();
-  if (act && eflag && avg_ok) {
-    double smin = 1.0;
-    for (int n = 0; n < NPE; ++n) smin = fmin(smin, sbuf[base + n]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Un[v] = smin * Un[v] + (1.0 - smin) * Ub[v];
-  }
-}
-
 template <int DIM, int P, int EOS>
 __global__ __launch_bounds__(256) void k_limit(LimArgs a) {
   using L = LimGeo<DIM, P>;
@@ -231,7 +177,7 @@ __global__ __launch_bounds__(256) void k_limit(LimArgs a) {
   }
   // (sbuf is rewritten by the operator only after every lane of the wave has read its
   // slopes: the reads above precede the ratio exchange's ordering point)
-  if (a.phys) physicality_wave<DIM, P>(u, act, tid, base, node, a.t, a.q, counter_slot(a.cnt), sbuf, sflag);
+  if (a.phys) physicality_wave<DIM, P, NT>(u, act, tid, base, node, a.t, a.q, counter_slot(a.cnt), sbuf, sflag);
   if (!act) return;
   // only the nodes the limiter or the operator changed are written (NaN compares unequal)
   bool changed = false;
