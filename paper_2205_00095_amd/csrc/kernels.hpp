@@ -1092,8 +1092,13 @@ __global__ __launch_bounds__((TileGeo<DIM, P>::NT), (elem_min_waves<DIM, P>())) 
     bool changed = true;
     if (a.phys) {
       // sF was last read in the volume phase, before the face phase's closing barrier
-      changed = physicality_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag, svote);
-      if (a.opflag && changed && (tid & 63) == 0) *a.opflag = 1u;
+      // (the FP32 vector-sweep form keeps the workgroup form and its single flag write:
+      // with the per-wave form that kernel spills past its register bound, 10% slower)
+      if constexpr (PREC == PREC_FP32)
+        changed = physicality_block_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag, svote);
+      else
+        changed = physicality_t<DIM, P, NT>(Un, act, tid, el, node, t, q, counter_slot(a.cnt), sF, sflag, svote);
+      if (a.opflag && changed && (PREC == PREC_FP32 ? tid == 0 : (tid & 63) == 0)) *a.opflag = 1u;
     }
     if (act) {
       if (a.za != 0.0) {
