@@ -50,6 +50,10 @@ RHS_CASES = [
     # c^4 ~ 1e34, for the reduced-precision division and root forms the build uses
     ("kh_paper", {"nx": 6, "p": 2, "c": 3.0e8}),
     ("kh_paper", {"nx": 5, "p": 3, "c": 3.0e8, "eos": wl.EOS_TM, "c2p": wl.C2P_NEWTON}),
+    # the same in SI units with HLLC, whose outer speeds enter as fractions multiplied
+    # together (products of c^5-sized numerators and c^4-sized denominators)
+    ("kh_paper", {"nx": 6, "p": 2, "c": 3.0e8, "flux": wl.FLUX_HLLC}),
+    ("kh_paper", {"nx": 5, "p": 3, "c": 3.0e8, "eos": wl.EOS_TM, "c2p": wl.C2P_NEWTON, "flux": wl.FLUX_HLLC}),
 ]
 
 
