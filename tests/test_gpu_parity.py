@@ -261,7 +261,9 @@ def test_enforce_matches_oracle(dim, p, n_elem):
                                               ("random3d", {"n_elem": (5, 4, 3)}, 1),
                                               ("kh_paper", {"nx": 6, "p": 2, "c": 3.0e8}, 3),
                                               ("kh_paper", {"nx": 5, "p": 3, "c": 3.0e8, "eos": wl.EOS_TM,
-                                                            "c2p": wl.C2P_NEWTON}, 3)])
+                                                            "c2p": wl.C2P_NEWTON}, 3),
+                                              ("kh_paper", {"nx": 5, "p": 3, "c": 3.0e8, "eos": wl.EOS_TM,
+                                                            "c2p": wl.C2P_NEWTON, "flux": wl.FLUX_HLLC}, 3)])
 def test_ssprk3_steps_match_oracle(kind, over, nsteps):
     cfg = _case_cfg(kind, over)
     st, U = oracle_state(cfg)
