@@ -197,7 +197,9 @@ __host__ __device__ __forceinline__ void state_flux_speed_rev(const double* W, i
   state_flux_speed_rev<EOS, DIM>(W, s, sp, d, q, lam_U_in, lam_F, lam_lm, lam_lp, with_speeds, lam_W);
 }
 
-// Adjoint of hll_flux(WL, WR, d): accumulates into lam_WL and lam_WR.
+// Adjoint of hll_flux(WL, WR, d): accumulates into lam_WL and lam_WR (the branch
+// chosen on the speeds as quotients, as the forward's fractions choose it except at
+// exact ties).
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void hll_flux_rev(const double* WL, const double* WR, int d, const PhysParams& q,
                                              const double* lam_Fh, double* lam_WL, double* lam_WR,
@@ -257,7 +259,9 @@ __host__ __device__ __forceinline__ void hll_flux_rev(const double* WL, const do
 }
 
 // Adjoint of hllc_flux(WL, WR, d): accumulates into lam_WL and lam_WR.  The forward
-// branch is retaken; in the star branch the reverse runs through the star state of
+// branch is retaken (chosen here on the speeds as quotients; the forward compares the
+// same speeds as fractions, which can choose otherwise only at exact ties, where the
+// flux is continuous); in the star branch the reverse runs through the star state of
 // the upwind side, the contact speed and pressure, the HLL state and flux rows they
 // use, and the outer speeds.
 template <int EOS, int DIM>
