@@ -265,9 +265,10 @@ __host__ __device__ __forceinline__ void hll_flux(const double* WL, const double
 // lambda*, lambda_R.
 //
 // Evaluated with two divisions: the outer speeds stay fractions n / den (den > 0) as in
-// hll_flux; the HLL state and flux are kept multiplied by Delta = (lambda_R - lambda_L)
-// den_L den_R > 0, which leaves lambda* unchanged (the quadratic is homogeneous in
-// them) and scales p* by Delta; and with lambda_K = n / den,
+// hll_flux, scaled by a power of two to den ~ 1; the HLL state and flux are kept
+// multiplied by Delta = (lambda_R - lambda_L) den_L den_R > 0, which leaves lambda*
+// unchanged (the quadratic is homogeneous in them) and scales p* by Delta; and with
+// lambda_K = n / den,
 //   F*_K = F_K + n (lambda* U_K - F_K + p* (0, e_d, lambda*)) / (n - lambda* den).
 template <int EOS, int DIM>
 __host__ __device__ __forceinline__ void hllc_flux(const double* WL, const double* WR, int d, const PhysParams& q,
@@ -284,14 +285,23 @@ __host__ __device__ __forceinline__ void hllc_flux(const double* WL, const doubl
   wavespeeds_nd<EOS, DIM>(WR, sR, d, q, nmR, npR, dnR);
   // lambda_L = nA / dA (the lesser lambda_-), lambda_R = nB / dB (the greater lambda_+)
   const bool lminL = nmL * dnR <= nmR * dnL;
-  const double nA = lminL ? nmL : nmR, dA = lminL ? dnL : dnR;
+  double nA = lminL ? nmL : nmR, dA = lminL ? dnL : dnR;
   const bool lmaxL = npL * dnR >= npR * dnL;
-  const double nB = lmaxL ? npL : npR, dB = lmaxL ? dnL : dnR;
+  double nB = lmaxL ? npL : npR, dB = lmaxL ? dnL : dnR;
   if (nA >= 0.0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) Fh[k] = FL[k];
     return;
   }
+  // the four scaled by one power of two to denominators near 1 (exact: the speeds and
+  // every result below are unchanged), so that the products below stay near the size of
+  // the states instead of growing with c^4 gamma^4 (Taub-Matthews, SI units)
+  int ex;
+  (void)frexp(fmax(dA, dB), &ex);
+  nA = ldexp(nA, -ex);
+  dA = ldexp(dA, -ex);
+  nB = ldexp(nB, -ex);
+  dB = ldexp(dB, -ex);
   // Delta times the HLL state and flux of the rows the contact needs (D, S_d, tau)
   const double cA = nA * dB, cB = nB * dA, cAB = dA * dB, cU = nA * nB;
   const double Dl = cB - cA;
